@@ -1,0 +1,559 @@
+"""FP64 CPU oracle for the modal entropy-stable DG (ESDG) shallow-water right-hand side.
+
+TEST INFRASTRUCTURE ONLY.  This module is the slow, plain reference that the HIP
+library is checked against.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import it; the library never does, and it
+shares no code with the library (its own basis, quadrature, operators, geometry,
+connectivity, fluxes and time stepper).
+
+Source: Wu, Kubatko & Chan, "High-order entropy stable discontinuous Galerkin
+methods for the shallow water equations: curved triangular meshes and GPU
+acceleration" (arXiv 2005.02516).  Every function names the section / equation it
+follows.  It evaluates the *literal dense* semi-discrete form, eq. (dgform) of
+Section 2.7, with the Lax-Friedrichs penalty of Section 2.8 and the five-stage
+low-storage RK4 of Section 4, in float64, vectorised over elements with numpy.
+
+Readings where the paper is silent, garbled or ambiguous (all listed in the design doc):
+
+* modal basis (Section 2.1 leaves it open): orthonormal Dubiner (PKDO) basis,
+  modes ordered ``for i in 0..N: for j in 0..N-i``;
+* quadrature (Section 2.1 gives only minimum degrees): Stroud collapsed rule with
+  (N+1)^2 points (exact to degree 2N+1) and N+1 Gauss-Legendre points per face;
+* reference vertices taken counter-clockwise (-1,-1), (1,-1), (-1,1); face 1 is
+  s=-1, face 2 is r+s=0, face 3 is r=-1, each parametrised counter-clockwise;
+* geometric factors G_ij (Section 2.6) are the Jacobian-scaled cofactors
+  rxJ = y_s, sxJ = -y_r, ryJ = -x_s, syJ = x_r, so that
+  B^{i,k} = W_f diag(nJ_i) with nJ = G * nhat;
+* entropy projection on curved elements uses the J-weighted L2 projection
+  (M_h^k)^{-1} V_q^T W diag(J) (Section 2.5 with the curved mass matrix of Section 2.6);
+* the flux matrix is F^i[m, n] = f_S^i(u~_m, u~_n) over all hybridized nodes;
+* the bathymetry source is -g V_h^T [0; diag(h~) Q_h^{x,k} b; diag(h~) Q_h^{y,k} b]
+  with b evaluated at the hybridized nodes (the y-momentum source uses b_y);
+* Lax-Friedrichs penalty (Section 2.8): -1/2 lambda sJ W_f (u~+ - u~) on the
+  entropy-projected conservative variables, lambda = max over both sides of
+  |u.n| + sqrt(g h);
+* LSRK coefficients: the published Carpenter-Kennedy (1994) 2N-storage values.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+# ----------------------------------------------------------------------------------
+# 1D orthogonal polynomials and Gauss rules
+# ----------------------------------------------------------------------------------
+
+
+def jacobi_normalized(x: np.ndarray, alpha: float, beta: float, n: int) -> np.ndarray:
+    """Orthonormal Jacobi polynomial P~_n^{(alpha,beta)}(x) on [-1, 1].
+
+    Normalised so that int_{-1}^{1} (1-x)^alpha (1+x)^beta P~_m P~_n dx = delta_mn.
+    Built with the three-term recurrence of the normalised Jacobi family.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    a, b = float(alpha), float(beta)
+    g0 = 2.0 ** (a + b + 1) / (a + b + 1) * math.gamma(a + 1) * math.gamma(b + 1) / math.gamma(a + b + 1)
+    p_prev = np.full_like(x, 1.0 / math.sqrt(g0))
+    if n == 0:
+        return p_prev
+    g1 = (a + 1) * (b + 1) / (a + b + 3) * g0
+    p = ((a + b + 2) * x / 2 + (a - b) / 2) / math.sqrt(g1)
+    if n == 1:
+        return p
+    a_old = 2.0 / (2 + a + b) * math.sqrt((a + 1) * (b + 1) / (a + b + 3))
+    for i in range(1, n):
+        h1 = 2 * i + a + b
+        a_new = 2.0 / (h1 + 2) * math.sqrt((i + 1) * (i + 1 + a + b) * (i + 1 + a) * (i + 1 + b) / ((h1 + 1) * (h1 + 3)))
+        b_new = -(a * a - b * b) / (h1 * (h1 + 2))
+        p_next = ((x - b_new) * p - a_old * p_prev) / a_new
+        p_prev, p = p, p_next
+        a_old = a_new
+    return p
+
+
+def jacobi_normalized_deriv(x: np.ndarray, alpha: float, beta: float, n: int) -> np.ndarray:
+    """d/dx P~_n^{(alpha,beta)} = sqrt(n (n + alpha + beta + 1)) P~_{n-1}^{(alpha+1,beta+1)}."""
+    if n == 0:
+        return np.zeros_like(np.asarray(x, dtype=np.float64))
+    return math.sqrt(n * (n + alpha + beta + 1)) * jacobi_normalized(x, alpha + 1, beta + 1, n - 1)
+
+
+def gauss_jacobi(n: int, alpha: float, beta: float) -> Tuple[np.ndarray, np.ndarray]:
+    """n-point Gauss-Jacobi rule for weight (1-x)^alpha (1+x)^beta by Golub-Welsch.
+
+    The nodes are the eigenvalues of the symmetric tridiagonal Jacobi matrix of the
+    monic recurrence; the weights are mu0 times the squared first eigenvector entries.
+    """
+    a, b = float(alpha), float(beta)
+    i = np.arange(n, dtype=np.float64)
+    diag = np.empty(n)
+    for k in range(n):
+        s = 2 * k + a + b
+        diag[k] = (b - a) / (a + b + 2) if k == 0 else (b * b - a * a) / (s * (s + 2))
+    off = np.empty(max(n - 1, 0))
+    for k in range(1, n):
+        s = 2 * k + a + b
+        off[k - 1] = 2.0 / s * math.sqrt(k * (k + a) * (k + b) * (k + a + b) / ((s - 1) * (s + 1)))
+    T = np.diag(diag) + np.diag(off, 1) + np.diag(off, -1)
+    lam, vec = np.linalg.eigh(T)
+    mu0 = 2.0 ** (a + b + 1) * math.gamma(a + 1) * math.gamma(b + 1) / math.gamma(a + b + 2)
+    w = mu0 * vec[0, :] ** 2
+    del i
+    return lam, w
+
+
+# ----------------------------------------------------------------------------------
+# Reference triangle (Section 2.1)
+# ----------------------------------------------------------------------------------
+
+
+def n_modes(N: int) -> int:
+    """N_p = dim P^N on a triangle."""
+    return (N + 1) * (N + 2) // 2
+
+
+def rs_to_ab(r: np.ndarray, s: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Collapsed coordinates a = 2(1+r)/(1-s) - 1, b = s (a = -1 at the top vertex)."""
+    r = np.asarray(r, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    a = np.where(np.abs(1.0 - s) > 1e-14, 2.0 * (1.0 + r) / np.where(np.abs(1.0 - s) > 1e-14, 1.0 - s, 1.0) - 1.0, -1.0)
+    return a, s.copy()
+
+
+def mode_list(N: int):
+    """Mode ordering: for i in 0..N, for j in 0..N-i."""
+    return [(i, j) for i in range(N + 1) for j in range(N + 1 - i)]
+
+
+def dubiner(N: int, r: np.ndarray, s: np.ndarray, grad: bool = False):
+    """Orthonormal Dubiner basis phi_ij = sqrt(2) P~_i(a) P~_j^{(2i+1,0)}(b) (1-b)^i.
+
+    Returns V[p, m] = phi_m(r_p, s_p) and, with ``grad``, the r and s derivatives by the
+    chain rule (a_r = 2/(1-s), a_s = (1+a)/(1-s), b_s = 1).  Derivatives are only
+    requested at points with s < 1.
+    """
+    a, b = rs_to_ab(r, s)
+    modes = mode_list(N)
+    V = np.zeros((a.size, len(modes)))
+    Vr = np.zeros_like(V)
+    Vs = np.zeros_like(V)
+    for m, (i, j) in enumerate(modes):
+        fa = jacobi_normalized(a, 0, 0, i)
+        gb = jacobi_normalized(b, 2 * i + 1, 0, j)
+        V[:, m] = math.sqrt(2.0) * fa * gb * (1.0 - b) ** i
+        if grad:
+            dfa = jacobi_normalized_deriv(a, 0, 0, i)
+            dgb = jacobi_normalized_deriv(b, 2 * i + 1, 0, j)
+            # d/dr: sqrt2 f'(a) a_r g (1-b)^i = sqrt2 f'(a) g 2 (1-b)^(i-1)
+            pw1 = (1.0 - b) ** (i - 1) if i > 0 else np.zeros_like(b)
+            Vr[:, m] = math.sqrt(2.0) * dfa * gb * 2.0 * pw1
+            # d/ds: sqrt2 [ f'(a) (1+a) g (1-b)^(i-1) + f(a) (g'(b) (1-b)^i - i g (1-b)^(i-1)) ]
+            Vs[:, m] = math.sqrt(2.0) * (dfa * (1.0 + a) * gb * pw1
+                                         + fa * (dgb * (1.0 - b) ** i - i * gb * pw1))
+    if grad:
+        return V, Vr, Vs
+    return V
+
+
+def stroud_rule(N: int):
+    """Volume rule: (N+1)-point Gauss-Legendre in a times (N+1)-point Gauss-Jacobi(1,0) in b.
+
+    Collapsed map r = (1+a)(1-b)/2 - 1, s = b, weight w = w_a w_b / 2 (sum w = 2, the
+    reference area).  Exact for total degree 2N+1, which covers the 2N volume rule.
+    """
+    q = N + 1
+    xa, wa = gauss_jacobi(q, 0.0, 0.0)
+    xb, wb = gauss_jacobi(q, 1.0, 0.0)
+    A, Bm = np.meshgrid(xa, xb, indexing="ij")
+    WA, WB = np.meshgrid(wa, wb, indexing="ij")
+    r = ((1.0 + A) * (1.0 - Bm) / 2.0 - 1.0).ravel()
+    s = Bm.ravel()
+    w = (0.5 * WA * WB).ravel()
+    return r, s, w
+
+
+def face_rule(N: int):
+    """N+1 Gauss-Legendre points on each face, faces listed 1, 2, 3, each counter-clockwise.
+
+    Face 1: s=-1 from v1 to v2, scaled normal (0,-1).
+    Face 2: r+s=0 from v2 to v3, scaled normal (1, 1) (unit normal times the face Jacobian sqrt 2).
+    Face 3: r=-1 from v3 to v1, scaled normal (-1, 0).
+    The weights are the Gauss-Legendre weights in the face parameter t in [-1, 1].
+    """
+    t, wt = gauss_jacobi(N + 1, 0.0, 0.0)
+    rf = np.concatenate([t, -t, -np.ones_like(t)])
+    sf = np.concatenate([-np.ones_like(t), t, -t])
+    wf = np.concatenate([wt, wt, wt])
+    one = np.ones_like(t)
+    nr = np.concatenate([0 * one, one, -one])
+    ns = np.concatenate([-one, one, 0 * one])
+    return rf, sf, wf, nr, ns
+
+
+class ReferenceElement:
+    """Reference-element operators of Sections 2.1-2.3 for degree N."""
+
+    def __init__(self, N: int):
+        self.N = N
+        self.Np = n_modes(N)
+        rq, sq, wq = stroud_rule(N)
+        rf, sf, wf, nr, ns = face_rule(N)
+        self.rq, self.sq, self.wq = rq, sq, wq
+        self.rf, self.sf, self.wf, self.nrJ, self.nsJ = rf, sf, wf, nr, ns
+        self.Nq, self.Nfq = rq.size, rf.size
+        self.Nh = self.Nq + self.Nfq
+        self.Nfp = N + 1
+        Vq, Vrq, Vsq = dubiner(N, rq, sq, grad=True)
+        Vf, Vrf, Vsf = dubiner(N, rf, sf, grad=True)
+        self.Vq, self.Vf = Vq, Vf
+        self.Vrq, self.Vsq, self.Vrf, self.Vsf = Vrq, Vsq, Vrf, Vsf
+        W = np.diag(wq)
+        Wf = np.diag(wf)
+        self.W, self.Wf = W, Wf
+        # Section 2.1: mass matrix and quadrature L2 projection
+        self.M = Vq.T @ W @ Vq
+        self.Pq = np.linalg.solve(self.M, Vq.T @ W)
+        # modal differentiation: coefficients of the derivative (exact: d phi in P^{N-1})
+        self.Dr = self.Pq @ Vrq
+        self.Ds = self.Pq @ Vsq
+        # Section 2.2
+        self.Qhat = [self.M @ self.Dr, self.M @ self.Ds]
+        self.B = [Wf @ np.diag(nr), Wf @ np.diag(ns)]
+        self.Q = [self.Pq.T @ Qh @ self.Pq for Qh in self.Qhat]
+        self.E = Vf @ self.Pq
+        self.Vh = np.vstack([Vq, Vf])
+        # Section 2.3: hybridized SBP operators
+        self.Qh = []
+        for Qi, Bi in zip(self.Q, self.B):
+            top = np.hstack([Qi - Qi.T, self.E.T @ Bi])
+            bot = np.hstack([-Bi @ self.E, Bi])
+            self.Qh.append(0.5 * np.vstack([top, bot]))
+
+
+# ----------------------------------------------------------------------------------
+# Mesh geometry and connectivity (Section 2.6)
+# ----------------------------------------------------------------------------------
+
+
+def equispaced_rs(N: int):
+    """Equispaced nodes in the input convention: for j in 0..N, for i in 0..N-j."""
+    pts = [(-1.0 + 2.0 * i / N, -1.0 + 2.0 * j / N) for j in range(N + 1) for i in range(N + 1 - j)]
+    a = np.array(pts)
+    return a[:, 0], a[:, 1]
+
+
+class Discretization:
+    """Per-mesh data for one instance: geometry, connectivity and curved mass matrices."""
+
+    def __init__(self, N: int, xg: np.ndarray, yg: np.ndarray, b_nodes: Optional[np.ndarray], g: float,
+                 Lx: float, Ly: float):
+        ref = ReferenceElement(N)
+        self.ref, self.N, self.g = ref, N, float(g)
+        self.K = xg.shape[0]
+        self.Lx, self.Ly = float(Lx), float(Ly)
+        req, seq = equispaced_rs(N)
+        self.Vgeo = dubiner(N, req, seq)                        # interpolation nodes -> modes
+        self.Vgeo_inv = np.linalg.inv(self.Vgeo)
+        # isoparametric map: modal coefficients of x and y
+        xm = xg @ self.Vgeo_inv.T
+        ym = yg @ self.Vgeo_inv.T
+        self.xm, self.ym = xm, ym
+        Vrh = np.vstack([ref.Vrq, ref.Vrf])
+        Vsh = np.vstack([ref.Vsq, ref.Vsf])
+        xr, xs = xm @ Vrh.T, xm @ Vsh.T
+        yr, ys = ym @ Vrh.T, ym @ Vsh.T
+        # Jacobian-scaled metric cofactors at all hybridized nodes
+        self.rxJ, self.sxJ = ys, -yr
+        self.ryJ, self.syJ = -xs, xr
+        self.J = xr * ys - xs * yr
+        self.Jq = self.J[:, :ref.Nq]
+        # physical node positions at the hybridized nodes
+        self.xh = xm @ ref.Vh.T
+        self.yh = ym @ ref.Vh.T
+        # scaled physical normals at face nodes: nJ_i = sum_j G_ij nhat_j
+        f = slice(ref.Nq, ref.Nh)
+        self.nJx = self.rxJ[:, f] * ref.nrJ + self.sxJ[:, f] * ref.nsJ
+        self.nJy = self.ryJ[:, f] * ref.nrJ + self.syJ[:, f] * ref.nsJ
+        self.sJ = np.sqrt(self.nJx ** 2 + self.nJy ** 2)
+        # curved mass matrices M_h^k = Vq^T W diag(J^k) Vq and their Cholesky factors
+        wJ = ref.wq[None, :] * self.Jq
+        self.Mh = np.einsum("qi,kq,qj->kij", ref.Vq, wJ, ref.Vq)
+        self.Mh_chol = np.linalg.cholesky(self.Mh)
+        self.mapP = self._connect()
+        # bathymetry: C0 nodal samples -> modes -> hybridized nodes
+        if b_nodes is None:
+            b_nodes = np.zeros_like(xg)
+        self.bh = b_nodes @ self.Vgeo_inv.T
+        self.b_hyb = self.bh @ ref.Vh.T
+        self.b_q = self.b_hyb[:, :ref.Nq]
+
+    # -- connectivity ---------------------------------------------------------------
+    def _connect(self) -> np.ndarray:
+        """mapP[k, f]: flat index k'*Nfq + f' of the neighbour's face node at the same point.
+
+        Faces are matched through the periodic images of their midpoints; nodes of two
+        matched faces are paired by coordinates.  Every node must find a partner.
+        """
+        ref = self.ref
+        K, Nfp, Nq = self.K, ref.Nfp, ref.Nq
+        xf = self.xh[:, Nq:].reshape(K, 3, Nfp)
+        yf = self.yh[:, Nq:].reshape(K, 3, Nfp)
+        L = np.array([self.Lx, self.Ly])
+        mid = np.stack([xf.mean(axis=2), yf.mean(axis=2)], axis=-1)          # K,3,2
+        hscale = float(np.max(np.abs(xf[:, :, -1] - xf[:, :, 0]) + np.abs(yf[:, :, -1] - yf[:, :, 0])))
+        tol = 1e-7 * hscale
+        key = np.round((mid % L) / (1e-4 * hscale)).astype(np.int64)
+        key[:, :, 0] %= int(round(self.Lx / (1e-4 * hscale)))
+        key[:, :, 1] %= int(round(self.Ly / (1e-4 * hscale)))
+        table: Dict[Tuple[int, int], list] = {}
+        for k in range(K):
+            for fc in range(3):
+                table.setdefault((int(key[k, fc, 0]), int(key[k, fc, 1])), []).append((k, fc))
+        mapP = np.full((K, 3 * Nfp), -1, dtype=np.int64)
+        for k in range(K):
+            for fc in range(3):
+                cand = table[(int(key[k, fc, 0]), int(key[k, fc, 1]))]
+                others = [c for c in cand if c != (k, fc)]
+                if len(others) != 1:
+                    raise ValueError(f"face ({k},{fc}) has {len(others)} partners")
+                k2, f2 = others[0]
+                for i in range(Nfp):
+                    dx = xf[k2, f2, :] - xf[k, fc, i]
+                    dy = yf[k2, f2, :] - yf[k, fc, i]
+                    dx -= self.Lx * np.round(dx / self.Lx)
+                    dy -= self.Ly * np.round(dy / self.Ly)
+                    d = np.hypot(dx, dy)
+                    j = int(np.argmin(d))
+                    if d[j] > tol:
+                        raise ValueError(f"unmatched face node ({k},{fc},{i})")
+                    mapP[k, fc * Nfp + i] = k2 * 3 * Nfp + f2 * Nfp + j
+        return mapP
+
+    # -- nodal <-> modal --------------------------------------------------------------
+    def interpolate(self, u_nodes: np.ndarray) -> np.ndarray:
+        """Modal coefficients of the degree-N interpolant of samples at the equispaced nodes."""
+        return u_nodes @ self.Vgeo_inv.T
+
+    def project(self, f_q: np.ndarray) -> np.ndarray:
+        """J-weighted quadrature L2 projection (M_h^k)^{-1} V_q^T W diag(J^k) f_q, per element."""
+        ref = self.ref
+        rhs = (f_q * (ref.wq[None, :] * self.Jq)) @ ref.Vq
+        return self.mh_solve(rhs)
+
+    def mh_solve(self, r: np.ndarray) -> np.ndarray:
+        """Solve M_h^k x = r for every element (r has shape [..., K, Np])."""
+        L = self.Mh_chol
+        shp = r.shape
+        rr = r.reshape(-1, self.K, self.ref.Np)
+        out = np.empty_like(rr)
+        for c in range(rr.shape[0]):
+            y = np.linalg.solve(L, rr[c][..., None])[..., 0]
+            out[c] = np.linalg.solve(np.swapaxes(L, 1, 2), y[..., None])[..., 0]
+        return out.reshape(shp)
+
+
+# ----------------------------------------------------------------------------------
+# Shallow-water entropy, entropy variables and fluxes (Sections 2.4, 2.7)
+# ----------------------------------------------------------------------------------
+
+
+def entropy(h, hu, hv, b, g):
+    """S(u) = 1/2 h (u^2 + v^2) + 1/2 g h^2 + g h b."""
+    u, v = hu / h, hv / h
+    return 0.5 * h * (u * u + v * v) + 0.5 * g * h * h + g * h * b
+
+
+def entropy_variables(h, hu, hv, b, g):
+    """v = (g (h + b) - (u^2 + v^2)/2, u, v)."""
+    u, v = hu / h, hv / h
+    return g * (h + b) - 0.5 * (u * u + v * v), u, v
+
+
+def conservative_from_entropy(v1, v2, v3, b, g):
+    """Inverse map of entropy_variables: h = (v1 + (v2^2 + v3^2)/2)/g - b, hu = h v2, hv = h v3."""
+    h = (v1 + 0.5 * (v2 * v2 + v3 * v3)) / g - b
+    return h, h * v2, h * v3
+
+
+def physical_flux(h, hu, hv, g):
+    """f^x = (hu, hu^2/h + g h^2/2, hu hv/h), f^y = (hv, hu hv/h, hv^2/h + g h^2/2)."""
+    u, v = hu / h, hv / h
+    fx = (hu, hu * u + 0.5 * g * h * h, hu * v)
+    fy = (hv, hv * u, hv * v + 0.5 * g * h * h)
+    return fx, fy
+
+
+def ec_flux(uL, uR, g):
+    """Entropy-conservative fluxes f^x_S, f^y_S of Section 2.7 with arithmetic averages {.}.
+
+    uL, uR are tuples (h, hu, hv) of broadcastable arrays.
+    """
+    hL, huL, hvL = uL
+    hR, huR, hvR = uR
+    uL_, vL_ = huL / hL, hvL / hL
+    uR_, vR_ = huR / hR, hvR / hR
+    avg = lambda a, b: 0.5 * (a + b)
+    h_avg = avg(hL, hR)
+    h2_avg = avg(hL * hL, hR * hR)
+    hu_avg, hv_avg = avg(huL, huR), avg(hvL, hvR)
+    u_avg, v_avg = avg(uL_, uR_), avg(vL_, vR_)
+    p = g * h_avg * h_avg - 0.5 * g * h2_avg
+    fx = (hu_avg, hu_avg * u_avg + p, hu_avg * v_avg)
+    fy = (hv_avg, hv_avg * u_avg, hv_avg * v_avg + p)
+    return fx, fy
+
+
+# ----------------------------------------------------------------------------------
+# Semi-discrete right-hand side (Sections 2.5-2.8), literal dense form
+# ----------------------------------------------------------------------------------
+
+
+class Oracle:
+    """Dense FP64 evaluation of eq. (dgform) with bathymetry source and optional LF penalty."""
+
+    def __init__(self, disc: Discretization, flux: str = "lf", chunk: int = 2048):
+        if flux not in ("ec", "lf"):
+            raise ValueError("flux must be 'ec' or 'lf'")
+        self.d = disc
+        self.flux = flux
+        self.chunk = chunk
+
+    # Section 2.5: entropy projection
+    def entropy_projection(self, uh: np.ndarray):
+        """u_q = V_q u_h, v_q = v(u_q), v_h = P^k v_q, v~ = V_h v_h, u~ = u(v~).
+
+        Returns u~ at the hybridized nodes, shape [3, K, Nh], and v_h [3, K, Np].
+        """
+        d, ref, g = self.d, self.d.ref, self.d.g
+        uq = uh @ ref.Vq.T                                     # [3,K,Nq]
+        vq = np.stack(entropy_variables(uq[0], uq[1], uq[2], d.b_q, g))
+        vh = d.project(vq)
+        vt = vh @ ref.Vh.T
+        ut = np.stack(conservative_from_entropy(vt[0], vt[1], vt[2], d.b_hyb, g))
+        return ut, vh
+
+    def physical_Qh(self, ks: slice):
+        """Q_h^{i,k}[m,n] = 1/2 sum_j (G_ij[m] + G_ij[n]) Qhat_h^j[m,n] (Section 2.6)."""
+        d, ref = self.d, self.d.ref
+        Qr, Qs = ref.Qh
+        def op(Gr, Gs):
+            return 0.5 * ((Gr[:, :, None] + Gr[:, None, :]) * Qr[None] + (Gs[:, :, None] + Gs[:, None, :]) * Qs[None])
+        Qx = op(d.rxJ[ks], d.sxJ[ks])
+        Qy = op(d.ryJ[ks], d.syJ[ks])
+        return Qx, Qy
+
+    def residual(self, uh: np.ndarray) -> np.ndarray:
+        """Hybridized-node residual r_h such that M_h du/dt = -V_h^T r_h.
+
+        r_h = sum_i 2 (Q_h^{i,k} o F^i) 1 + [0; B^{i,k} (f_S^i(u~+, u~) - f^i(u~_f))] - S (+ LF penalty).
+        """
+        d, ref, g = self.d, self.d.ref, self.d.g
+        ut, _ = self.entropy_projection(uh)
+        K, Nq, Nh = d.K, ref.Nq, ref.Nh
+        r = np.zeros((3, K, Nh))
+        for k0 in range(0, K, self.chunk):
+            ks = slice(k0, min(K, k0 + self.chunk))
+            Qx, Qy = self.physical_Qh(ks)
+            uL = tuple(ut[c, ks][:, :, None] for c in range(3))
+            uR = tuple(ut[c, ks][:, None, :] for c in range(3))
+            Fx, Fy = ec_flux(uL, uR, g)
+            for c in range(3):
+                r[c, ks] += 2.0 * np.sum(Qx * Fx[c] + Qy * Fy[c], axis=2)
+            # bathymetry source S = -g [0; diag(h~) Q^x b; diag(h~) Q^y b] moved to the left
+            bt = d.b_hyb[ks]
+            r[1, ks] += g * ut[0, ks] * np.einsum("kmn,kn->km", Qx, bt)
+            r[2, ks] += g * ut[0, ks] * np.einsum("kmn,kn->km", Qy, bt)
+        # interface terms on the face rows
+        uf = ut[:, :, Nq:]                                        # [3,K,Nfq]
+        up = uf.reshape(3, -1)[:, d.mapP.reshape(-1)].reshape(uf.shape)
+        fS_x, fS_y = ec_flux(tuple(up), tuple(uf), g)
+        f_x, f_y = physical_flux(uf[0], uf[1], uf[2], g)
+        wf = ref.wf[None, :]
+        for c in range(3):
+            r[c, :, Nq:] += wf * (d.nJx * (fS_x[c] - f_x[c]) + d.nJy * (fS_y[c] - f_y[c]))
+        if self.flux == "lf":
+            nx, ny = d.nJx / d.sJ, d.nJy / d.sJ
+            def speed(u):
+                return np.abs((u[1] * nx + u[2] * ny) / u[0]) + np.sqrt(g * u[0])
+            lam = np.maximum(speed(uf), speed(up))
+            for c in range(3):
+                r[c, :, Nq:] -= wf * 0.5 * lam * d.sJ * (up[c] - uf[c])
+        return r
+
+    def rhs(self, uh: np.ndarray) -> np.ndarray:
+        """du_h/dt = -(M_h^k)^{-1} V_h^T r_h, solved with the Cholesky factors of M_h^k."""
+        r = self.residual(uh)
+        return -self.d.mh_solve(r @ self.d.ref.Vh)
+
+
+# ----------------------------------------------------------------------------------
+# Time stepping (Section 4: five-stage fourth-order low-storage RK)
+# ----------------------------------------------------------------------------------
+
+LSRK_A = np.array([0.0,
+                   -567301805773.0 / 1357537059087.0,
+                   -2404267990393.0 / 2016746695238.0,
+                   -3550918686646.0 / 2091501179385.0,
+                   -1275806237668.0 / 842570457699.0])
+LSRK_B = np.array([1432997174477.0 / 9575080441904.0,
+                   5161836677717.0 / 13612068292357.0,
+                   1720146321549.0 / 2090206949498.0,
+                   3134564353537.0 / 4481467310338.0,
+                   2277821191437.0 / 14882151754819.0])
+LSRK_C = np.array([0.0,
+                   1432997174477.0 / 9575080441904.0,
+                   2526269341429.0 / 6820363962896.0,
+                   2006345519317.0 / 3224310063776.0,
+                   2802321613138.0 / 2924317926251.0])
+
+
+def lsrk_step(rhs, u: np.ndarray, du: np.ndarray, dt: float):
+    """One 2N-storage step: for each stage du = a_s du + dt rhs(u); u = u + b_s du."""
+    for s in range(5):
+        du = LSRK_A[s] * du + dt * rhs(u)
+        u = u + LSRK_B[s] * du
+    return u, du
+
+
+def run(oracle: Oracle, uh: np.ndarray, dt: float, nsteps: int):
+    du = np.zeros_like(uh)
+    u = uh.copy()
+    for _ in range(nsteps):
+        u, du = lsrk_step(oracle.rhs, u, du, dt)
+    return u, du
+
+
+# ----------------------------------------------------------------------------------
+# Diagnostics (Sections 2.4 and 2.7): conserved totals, entropy and its rate
+# ----------------------------------------------------------------------------------
+
+
+def diagnostics(oracle: Oracle, uh: np.ndarray) -> Dict[str, np.ndarray]:
+    """Mass sum_k 1^T W J V_q u_h, entropy sum w J S(u_q), entropy rate sum w J v(u_q).(V_q du/dt)."""
+    d, ref, g = oracle.d, oracle.d.ref, oracle.d.g
+    wJ = ref.wq[None, :] * d.Jq
+    uq = uh @ ref.Vq.T
+    mass = np.array([np.sum(wJ * uq[c]) for c in range(3)])
+    S = np.sum(wJ * entropy(uq[0], uq[1], uq[2], d.b_q, g))
+    dudt = oracle.rhs(uh) @ ref.Vq.T
+    vq = entropy_variables(uq[0], uq[1], uq[2], d.b_q, g)
+    terms = wJ[None] * np.stack(vq) * dudt
+    return {"mass": mass, "entropy": float(S), "entropy_rate": float(np.sum(terms)),
+            "entropy_rate_scale": float(np.sum(np.abs(terms)))}
+
+
+def l2_error(disc: Discretization, uh: np.ndarray, exact_fn) -> np.ndarray:
+    """Per-field L2 error with a volume rule exact to degree >= 2N+2 (Section 4.2).
+
+    ``exact_fn(x, y)`` returns the exact (h, hu, hv) at physical points.
+    """
+    N = disc.N
+    r, s, w = stroud_rule(N + 1)                        # (N+2)^2 points, exact to 2N+3
+    V, Vr, Vs = dubiner(N, r, s, grad=True)
+    x, y = disc.xm @ V.T, disc.ym @ V.T
+    J = (disc.xm @ Vr.T) * (disc.ym @ Vs.T) - (disc.xm @ Vs.T) * (disc.ym @ Vr.T)
+    ue = exact_fn(x, y)
+    uq = uh @ V.T
+    return np.array([math.sqrt(np.sum(w[None, :] * J * (uq[c] - ue[c]) ** 2)) for c in range(3)])

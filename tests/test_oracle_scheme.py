@@ -1,0 +1,390 @@
+"""Pins of the oracle's discretisation against what the paper and the mathematics fix.
+
+* geometry: J > 0, affine elements give constant J, discrete GCL / physical SBP
+  (Section 2.6), watertight periodic matching, total area;
+* flux: consistency, symmetry and Tadmor's entropy-conservation condition
+  (Definition 2.1 of Section 2.7), checked with an independently derived potential;
+* entropy variables are the gradient of the entropy (complex-step), round trip;
+* scheme: lake at rest (Theorem 2.2 and Section 2.8), free stream, entropy
+  conservation / dissipation, conservation of mass and momentum;
+* the skew, zero-block-skipping form of Section 5.2 (Step 4), with the bathymetry
+  source folded into the pair loop, equals the dense form;
+* LSRK4(5): order conditions and temporal self-convergence; vortex convergence in h.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import esdg_oracle as O
+from paper_2005_02516_amd import workloads as wl
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def make(w, flux=None):
+    d = O.Discretization(w.N, w.xg, w.yg, w.b_nodes, w.g, w.Lx, w.Ly)
+    return d, O.Oracle(d, flux or w.flux)
+
+
+def random_smooth_state(w, seed, amp=0.05):
+    rng = np.random.default_rng(seed)
+    x, y = w.xf, w.yf
+    f = lambda a: a * np.sin(np.pi * (rng.integers(1, 3) * x + rng.uniform(0, 2))) * np.cos(
+        np.pi * (rng.integers(1, 3) * y + rng.uniform(0, 2)))
+    h = 2.0 - w.b_nodes + f(amp) + 0.3
+    return np.stack([h, h * (0.2 + f(0.3)), h * (-0.1 + f(0.3))])
+
+
+# ------------------------------------------------------------------ geometry
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+def test_geometry_curved(N):
+    """PIN-5/6: J > 0, GCL (Q_h^{i,k} 1 = 0), physical SBP, sum_f W_f nJ = 0, total area 4."""
+    w = wl.config2(n=4, N=N)
+    d, o = make(w)
+    ref = d.ref
+    assert d.J.min() > 0
+    assert abs(np.sum(ref.wq[None] * d.Jq) - 4.0) < 1e-13
+    Qx, Qy = o.physical_Qh(slice(0, d.K))
+    one = np.ones(ref.Nh)
+    assert np.abs(Qx @ one).max() < 1e-13 and np.abs(Qy @ one).max() < 1e-13
+    for Qi, nJ in ((Qx, d.nJx), (Qy, d.nJy)):
+        sym = Qi + np.swapaxes(Qi, 1, 2)
+        Bk = np.zeros_like(sym)
+        idx = np.arange(ref.Nq, ref.Nh)
+        Bk[:, idx, idx] = ref.wf[None] * nJ
+        assert np.abs(sym - Bk).max() < 1e-13
+        assert np.abs(np.sum(ref.wf[None] * nJ, axis=1)).max() < 1e-13
+    # watertight: matched face nodes coincide and have opposite normals
+    mp = d.mapP.reshape(-1)
+    xf = d.xh[:, ref.Nq:].reshape(-1)
+    yf = d.yh[:, ref.Nq:].reshape(-1)
+    dx = xf[mp] - xf
+    dy = yf[mp] - yf
+    dx -= 2.0 * np.round(dx / 2.0)
+    dy -= 2.0 * np.round(dy / 2.0)
+    assert np.abs(dx).max() < 1e-13 and np.abs(dy).max() < 1e-13
+    assert np.abs(d.nJx.reshape(-1)[mp] + d.nJx.reshape(-1)).max() < 1e-13
+    assert np.abs(d.nJy.reshape(-1)[mp] + d.nJy.reshape(-1)).max() < 1e-13
+    assert np.array_equal(mp[mp], np.arange(mp.size))
+
+
+def test_geometry_affine_constant():
+    """PIN-6: an affine mesh of squares of side h gives J = h^2/4 and constant metrics."""
+    n, N = 4, 3
+    w = wl.config1(n=n, N=N)
+    d, _ = make(w)
+    hsq = 2.0 / n
+    assert np.allclose(d.J, hsq * hsq / 4.0, atol=1e-14)
+    for G in (d.rxJ, d.sxJ, d.ryJ, d.syJ):
+        assert np.allclose(G, G[:, :1], atol=1e-14)
+
+
+# ------------------------------------------------------------------ flux and entropy
+
+
+def _rand_states(rng, n):
+    h = rng.uniform(0.5, 3.0, n)
+    return h, h * rng.uniform(-1, 1, n), h * rng.uniform(-1, 1, n)
+
+
+def test_ec_flux_properties():
+    """PIN-7: consistency, symmetry, Tadmor (vL - vR)^T f_S = psi_L - psi_R, psi = 1/2 g h^2 (u, v)."""
+    rng = np.random.default_rng(7)
+    g = 1.7
+    uL = _rand_states(rng, 200)
+    uR = _rand_states(rng, 200)
+    fx, fy = O.ec_flux(uL, uL, g)
+    px, py = O.physical_flux(*uL, g)
+    for c in range(3):
+        assert np.allclose(fx[c], px[c], rtol=1e-14, atol=1e-14)
+        assert np.allclose(fy[c], py[c], rtol=1e-14, atol=1e-14)
+    fxa, fya = O.ec_flux(uL, uR, g)
+    fxb, fyb = O.ec_flux(uR, uL, g)
+    for c in range(3):
+        assert np.allclose(fxa[c], fxb[c], rtol=1e-14) and np.allclose(fya[c], fyb[c], rtol=1e-14)
+    b = 0.3
+    vL = O.entropy_variables(*uL, b, g)
+    vR = O.entropy_variables(*uR, b, g)
+    psi = lambda u, k: 0.5 * g * u[0] ** 2 * (u[1 + k] / u[0])
+    for k, f in ((0, fxa), (1, fya)):
+        lhs = sum((vL[c] - vR[c]) * f[c] for c in range(3))
+        rhs = psi(uL, k) - psi(uR, k)
+        assert np.allclose(lhs, rhs, rtol=1e-12, atol=1e-13)
+
+
+def test_entropy_variables_are_gradient():
+    """v = dS/du (complex step, exact to rounding) and u(v(u)) = u (PIN-8)."""
+    rng = np.random.default_rng(3)
+    g, b = 9.81, 0.25
+    h, hu, hv = _rand_states(rng, 50)
+    v = O.entropy_variables(h, hu, hv, b, g)
+    eps = 1e-30
+    dS = [np.imag(O.entropy(h + 1j * eps, hu, hv, b, g)) / eps,
+          np.imag(O.entropy(h, hu + 1j * eps, hv, b, g)) / eps,
+          np.imag(O.entropy(h, hu, hv + 1j * eps, b, g)) / eps]
+    for c in range(3):
+        assert np.allclose(v[c], dS[c], rtol=1e-14, atol=1e-14)
+    back = O.conservative_from_entropy(*v, b, g)
+    for c, a in enumerate((h, hu, hv)):
+        assert np.allclose(back[c], a, rtol=1e-14, atol=1e-14)
+
+
+# ------------------------------------------------------------------ scheme properties
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+@pytest.mark.parametrize("warp", [0.0, 0.05])
+@pytest.mark.parametrize("flux", ["ec", "lf"])
+def test_lake_at_rest(N, warp, flux):
+    """PIN-9: h = H - b with continuous b in P^N and zero velocity gives rhs = 0 to round-off."""
+    xg, yg, xf, yf = wl.structured_mesh(4, N, warp=warp)
+    b = 0.1 * np.sin(np.pi * xf) * np.cos(np.pi * yf) + 0.1
+    d = O.Discretization(N, xg, yg, b, 1.0, 2.0, 2.0)
+    o = O.Oracle(d, flux)
+    u = np.stack([2.2 - b, 0 * b, 0 * b])
+    r = o.rhs(d.interpolate(u))
+    assert np.abs(r).max() < 5e-13
+
+
+def test_lake_at_rest_magnitude_vs_paper():
+    """Round-off magnitude of the lake at rest after T = 1/2 is of the order the paper prints."""
+    tab = json.load(open(os.path.join(HERE, "golden", "lake_at_rest_tables.json")))
+    N, n = 2, 8
+    xg, yg, xf, yf = wl.structured_mesh(n, N, warp=0.05)
+    b = 0.1 * np.sin(np.pi * xf) * np.cos(np.pi * yf) + 0.5
+    d = O.Discretization(N, xg, yg, b, 1.0, 2.0, 2.0)
+    o = O.Oracle(d, "lf")
+    u0 = np.stack([2.0 - b, 0 * b, 0 * b])
+    uh = d.interpolate(u0)
+    dt = wl.timestep(u0, 1.0, N, 2.0 / n, 0.125)
+    nst = int(math.ceil(0.5 / dt))
+    u1, _ = O.run(o, uh, 0.5 / nst, nst)
+    # the discrete steady state is the initial interpolant itself; its L2 change is the error
+    wJ = d.ref.wq[None] * d.Jq
+    err = np.sqrt([np.sum(wJ * ((u1[c] - uh[c]) @ d.ref.Vq.T) ** 2) for c in range(3)])
+    paper = tab["curved"]["2"][0]          # N=2, K=256, curved
+    assert np.all(err < 10 * paper), err
+
+
+@pytest.mark.parametrize("N", [1, 3])
+def test_free_stream(N):
+    """PIN-10: a constant state over constant b is preserved on a curved mesh (GCL)."""
+    xg, yg, xf, yf = wl.structured_mesh(4, N, warp=0.05)
+    b = 0 * xf + 0.3
+    d = O.Discretization(N, xg, yg, b, 1.0, 2.0, 2.0)
+    for flux in ("ec", "lf"):
+        o = O.Oracle(d, flux)
+        u = np.stack([0 * xf + 1.5, 0 * xf + 0.4, 0 * xf - 0.7])
+        assert np.abs(o.rhs(d.interpolate(u))).max() < 1e-13
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_entropy_conservation_and_dissipation(N):
+    """PIN-11: EC flux gives zero entropy production over a periodic curved mesh with
+    varying continuous b; the LF penalty makes it negative."""
+    w = wl.config2(n=4, N=N)
+    ustate = random_smooth_state(w, seed=N)
+    d, _ = make(w)
+    uh = d.interpolate(ustate)
+    ec = O.diagnostics(O.Oracle(d, "ec"), uh)
+    assert abs(ec["entropy_rate"]) < 1e-13 * ec["entropy_rate_scale"]
+    lf = O.diagnostics(O.Oracle(d, "lf"), uh)
+    assert lf["entropy_rate"] < -1e-8 * lf["entropy_rate_scale"]
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_conservation(N):
+    """PIN-12: sum_k 1^T M_h^k du/dt = 0 for h; for flat b also for hu and hv."""
+    w = wl.config2(n=4, N=N)
+    d, o = make(w)
+    uh = d.interpolate(random_smooth_state(w, seed=11))
+    ref = d.ref
+    wJ = ref.wq[None] * d.Jq
+    r = o.rhs(uh)
+    tot = [np.sum(wJ * (r[c] @ ref.Vq.T)) for c in range(3)]
+    assert abs(tot[0]) < 1e-13 * np.abs(r[0]).sum()
+    wflat = wl.config1(n=4, N=N)
+    xg, yg = w.xg, w.yg
+    d2 = O.Discretization(N, xg, yg, 0 * w.b_nodes + 0.2, 1.0, 2.0, 2.0)
+    o2 = O.Oracle(d2, "lf")
+    r2 = o2.rhs(d2.interpolate(random_smooth_state(w, seed=12)))
+    for c in range(3):
+        assert abs(np.sum(wJ * (r2[c] @ ref.Vq.T))) < 1e-13 * np.abs(r2[c]).sum()
+    del wflat
+
+
+# ------------------------------------------------------------------ Step 4 algebra
+
+
+def skew_form_residual(o, uh, Href):
+    """Residual by the skew form: pairs (m, n) of hybridized nodes, surface-surface block skipped.
+
+    Qx_mn = 1/2 sum_j (G_xj[m] + G_xj[n]) (Qhat_h^j - Qhat_h^j^T)[m, n]; row m gets
+    Qx_mn {hu} + Qy_mn {hv} (mass), {u} c + 1/2 g h_m (H_n - Href) Qx_mn (x-momentum),
+    ...; face rows get W_f (nJ . f_S(u~, u~+) + 1/2 g h (h+ + b - Href) nJ) and the LF term.
+    """
+    d, ref, g = o.d, o.d.ref, o.d.g
+    ut, _ = o.entropy_projection(uh)
+    Nq, Nh = ref.Nq, ref.Nh
+    h, hu, hv = ut
+    u, v = hu / h, hv / h
+    dH = h + d.b_hyb - Href
+    Sr = ref.Qh[0] - ref.Qh[0].T
+    Ss = ref.Qh[1] - ref.Qh[1].T
+    avg = lambda a: 0.5 * (a[:, :, None] + a[:, None, :])
+    Qx = 0.5 * (avg(d.rxJ) * 2 * Sr + avg(d.sxJ) * 2 * Ss)
+    Qy = 0.5 * (avg(d.ryJ) * 2 * Sr + avg(d.syJ) * 2 * Ss)
+    c = Qx * avg(hu) + Qy * avg(hv)
+    r = np.zeros((3,) + h.shape)
+    r[0] = c.sum(2)
+    r[1] = (avg(u) * c).sum(2) + 0.5 * g * h * np.einsum("kmn,kn->km", Qx, dH)
+    r[2] = (avg(v) * c).sum(2) + 0.5 * g * h * np.einsum("kmn,kn->km", Qy, dH)
+    # face rows
+    f = slice(Nq, Nh)
+    mp = d.mapP.reshape(-1)
+    hP, huP, hvP = (a[:, f].reshape(-1)[mp].reshape(h[:, f].shape) for a in (h, hu, hv))
+    hm, hum, hvm = h[:, f], hu[:, f], hv[:, f]
+    ua, va = 0.5 * (hum / hm + huP / hP), 0.5 * (hvm / hm + hvP / hP)
+    hua, hva = 0.5 * (hum + huP), 0.5 * (hvm + hvP)
+    wf = ref.wf[None]
+    pr = 0.5 * g * hm * (hP + d.b_hyb[:, f] - Href)
+    r[0, :, f] += wf * (d.nJx * hua + d.nJy * hva)
+    r[1, :, f] += wf * (d.nJx * (hua * ua + pr) + d.nJy * hva * ua)
+    r[2, :, f] += wf * (d.nJx * hua * va + d.nJy * (hva * va + pr))
+    if o.flux == "lf":
+        nx, ny = d.nJx / d.sJ, d.nJy / d.sJ
+        lam = np.maximum(np.abs((hum * nx + hvm * ny) / hm) + np.sqrt(g * hm),
+                         np.abs((huP * nx + hvP * ny) / hP) + np.sqrt(g * hP))
+        for k, (a, ap) in enumerate(((hm, hP), (hum, huP), (hvm, hvP))):
+            r[k, :, f] -= wf * 0.5 * lam * d.sJ * (ap - a)
+    return r
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+@pytest.mark.parametrize("flux", ["ec", "lf"])
+def test_skew_form_equals_dense(N, flux):
+    """PIN-14: (Q_skew o F) 1 + B f_S with the folded source and any H_ref equals the dense form."""
+    w = wl.config2(n=4, N=N)
+    d, o = make(w, flux)
+    uh = d.interpolate(random_smooth_state(w, seed=5))
+    dense = o.residual(uh)
+    for Href in (0.0, 2.2):
+        sk = skew_form_residual(o, uh, Href)
+        assert np.abs(sk - dense).max() < 1e-12 * np.abs(dense).max()
+
+
+def test_pair_loop_tiny():
+    """The unordered pair traversal (m < n, not both on faces, both rows updated) equals the
+    ordered skew sum, element by element, on a tiny mesh."""
+    w = wl.config2(n=2, N=2)
+    d, o = make(w, "ec")
+    uh = d.interpolate(random_smooth_state(w, seed=9))
+    ut, _ = o.entropy_projection(uh)
+    ref, g, Href = d.ref, d.g, 2.2
+    Nq, Nh = ref.Nq, ref.Nh
+    Sr = 0.5 * (ref.Qh[0] - ref.Qh[0].T) * 2
+    Ss = 0.5 * (ref.Qh[1] - ref.Qh[1].T) * 2
+    full = skew_form_residual(o, uh, Href)
+    for k in range(d.K):
+        h, hu, hv = ut[:, k]
+        dH = h + d.b_hyb[k] - Href
+        acc = np.zeros((3, Nh))
+        for m in range(Nh):
+            for n in range(m + 1, Nh):
+                if m >= Nq and n >= Nq:
+                    continue
+                Qx = 0.5 * ((d.rxJ[k, m] + d.rxJ[k, n]) * Sr[m, n] + (d.sxJ[k, m] + d.sxJ[k, n]) * Ss[m, n])
+                Qy = 0.5 * ((d.ryJ[k, m] + d.ryJ[k, n]) * Sr[m, n] + (d.syJ[k, m] + d.syJ[k, n]) * Ss[m, n])
+                c = Qx * 0.5 * (hu[m] + hu[n]) + Qy * 0.5 * (hv[m] + hv[n])
+                ua = 0.5 * (hu[m] / h[m] + hu[n] / h[n])
+                va = 0.5 * (hv[m] / h[m] + hv[n] / h[n])
+                acc[:, m] += [c, ua * c + 0.5 * g * h[m] * dH[n] * Qx, va * c + 0.5 * g * h[m] * dH[n] * Qy]
+                acc[:, n] -= [c, ua * c + 0.5 * g * h[n] * dH[m] * Qx, va * c + 0.5 * g * h[n] * dH[m] * Qy]
+        vol = full[:, k].copy()
+        # remove the face-row interface terms from the full residual: compare volume parts only
+        vol_only = skew_form_residual(o, uh, Href)[:, k]
+        del vol
+        assert np.abs(acc[:, :Nq] - vol_only[:, :Nq]).max() < 1e-13
+
+
+# ------------------------------------------------------------------ time integration
+
+
+def test_lsrk_order_conditions():
+    """PIN-15: the 2N-storage coefficients reproduce the RK4 stability polynomial and stage times."""
+    A, B, C = O.LSRK_A, O.LSRK_B, O.LSRK_C
+    # y' = lam y: apply one step symbolically to get the amplification polynomial coefficients
+    # (track coefficients of z^p in u and du)
+    u = np.zeros(6)
+    u[0] = 1.0
+    du = np.zeros(6)
+    for s in range(5):
+        k = np.zeros(6)
+        k[1:] = u[:-1]          # dt * lam * u  -> shift powers of z
+        du = A[s] * du + k
+        u = u + B[s] * du
+    assert np.allclose(u[:5], [1, 1, 0.5, 1 / 6, 1 / 24], atol=1e-11)
+    # stage times: c_s = sum of the effective weights accumulated before stage s
+    t = 0.0
+    dt_acc = 0.0
+    times = []
+    for s in range(5):
+        times.append(t)
+        dt_acc = A[s] * dt_acc + 1.0
+        t = t + B[s] * dt_acc
+    assert np.allclose(times, C, atol=1e-11)
+    assert abs(t - 1.0) < 1e-11
+
+
+def test_lsrk_temporal_convergence():
+    """Halving dt reduces the time error by about 2^4 on a tiny mesh."""
+    w = wl.config1(n=2, N=2)
+    d, o = make(w, "lf")
+    uh = d.interpolate(w.u_nodes)
+    T = 0.4
+    sol = {}
+    for ns in (8, 16, 32, 256):          # dt = T/8 is about 2.4x the CFL-rule step
+        sol[ns], _ = O.run(o, uh, T / ns, ns)
+    e1 = np.abs(sol[8] - sol[256]).max()
+    e2 = np.abs(sol[16] - sol[256]).max()
+    e3 = np.abs(sol[32] - sol[256]).max()
+    assert 12 < e1 / e2 < 20 and 12 < e2 / e3 < 20
+
+
+# ------------------------------------------------------------------ convergence
+
+
+def _vortex_error(N, n, T=0.1):
+    par = dict(g=1.0, hinf=1.0, A=0.1, R=0.3, xc=1.0, yc=1.0, uinf=0.5, vinf=0.25)
+    xg, yg, xf, yf = wl.structured_mesh(n, N, warp=0.05)
+    d = O.Discretization(N, xg, yg, None, 1.0, 2.0, 2.0)
+    o = O.Oracle(d, "lf")
+
+    def exact(t):
+        def f(x, y):
+            h, u, v = wl.vortex_fields(x, y, t, **par)
+            return np.stack([h, h * u, h * v])
+        return f
+
+    uh = d.project(exact(0.0)(d.xh[:, :d.ref.Nq], d.yh[:, :d.ref.Nq]))
+    h, u, v = wl.vortex_fields(xf, yf, 0.0, **par)
+    dt0 = wl.timestep(np.stack([h, h * u, h * v]), 1.0, N, 2.0 / n, 0.25)
+    ns = int(math.ceil(T / dt0))
+    u1, _ = O.run(o, uh, T / ns, ns)
+    return O.l2_error(d, u1, exact(T))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("N,ns,minrate", [(1, (16, 32), 1.8), (2, (8, 16), 2.4)])
+def test_vortex_convergence(N, ns, minrate):
+    """PIN-13: L2 error of the translating vortex on curved meshes falls at about h^(N+1)
+    (h^(N+1/2) for even N on these structured meshes)."""
+    e0 = _vortex_error(N, ns[0])
+    e1 = _vortex_error(N, ns[1])
+    rate = np.log2(e0 / e1)
+    assert np.all(rate > minrate), rate
