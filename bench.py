@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Throughput benchmark: DOF-updates/s per RK stage of the ESDG shallow-water solver.
+
+Workload (N=3, the degree the metric is quoted at): periodic [0,2]^2, 64x64 squares split
+into 8192 curved triangles (nodes warped by 0.05 sin(pi x) sin(pi y)), bathymetry
+b = 0.1 sin(pi x) cos(pi y) + 0.1, lake at rest H = 2.2 plus a seeded Gaussian bump of
+amplitude 0.01, Lax-Friedrichs interface flux, g = 1.  A step is one LSRK4(5) step
+(five fused RK-stage launches, replayed from HIP graphs); inputs are resident in HBM
+before the timed region.  value = K * Np / (time per RK stage), FP32 bulk path with FP64
+entropy round trip; the FP64 path is timed on the same workload for the speedup.
+
+Prints one JSON line.  Only one GPU is supported: --gpus > 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+PEAK_FP32_TFLOPS = 157.3       # MI355X vector FP32 (published)
+PEAK_FP64_TFLOPS = 78.6        # MI355X vector FP64 (published)
+
+
+def pairs(N):
+    Nq, Nfq = (N + 1) ** 2, 3 * (N + 1)
+    return Nq * (Nq - 1) // 2 + Nq * Nfq
+
+
+def dims(N):
+    Np = (N + 1) * (N + 2) // 2
+    Nq, Nfq = (N + 1) ** 2, 3 * (N + 1)
+    return Np, Nq, Nfq, Nq + Nfq
+
+
+def alg_flops_per_elem(N):
+    """35 FLOP per unordered nonzero node pair (flux differencing) + projection and lift
+    contractions 6(2 Nq Np + Np^2 + Nh Np) + 6(Np Nh + Np^2)."""
+    Np, Nq, Nfq, Nh = dims(N)
+    return 35 * pairs(N) + 6 * (2 * Nq * Np + Np * Np + Nh * Np) + 6 * (Np * Nh + Np * Np)
+
+
+def alg_bytes_per_elem(N, word):
+    """Minimum HBM bytes per element per stage: state 12 Np words (read u_h; read and write
+    du; write u_h), face exchange 6 Nfq, geometry 2 Np (node coordinates), bathymetry Np,
+    and the curved inverse mass matrix Np^2."""
+    Np, Nq, Nfq, Nh = dims(N)
+    return word * (12 * Np + 6 * Nfq + 2 * Np + Np + Np * Np)
+
+
+def time_steps(s, dt, steps, torch):
+    """Event-timed region on the solver's stream: returns milliseconds for `steps` steps."""
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(s.stream)
+    s.step(dt, steps)
+    ev1.record(s.stream)
+    ev1.synchronize()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1)
+
+
+def cpu_baseline(w, stages_budget=15):
+    """The FP64 oracle as it stands, timed on this host: `stages_budget` RK stages of the
+    same workload (one RHS + axpy each), BLAS pinned to one thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import esdg_oracle as O
+    d = O.Discretization(w.N, w.xg, w.yg, w.b_nodes, w.g, w.Lx, w.Ly)
+    o = O.Oracle(d, w.flux)
+    uh = d.interpolate(w.u_nodes)
+    du = np.zeros_like(uh)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        for s in range(stages_budget):
+            du = O.LSRK_A[s % 5] * du + w.dt * o.rhs(uh)
+            uh = uh + O.LSRK_B[s % 5] * du
+        t = time.perf_counter() - t0
+    Np = dims(w.N)[0]
+    return {"value": w.K * Np * stages_budget / t, "unit": "DOF-updates/s per RK stage", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{stages_budget} RK stages ({stages_budget // 5} LSRK steps) of the same {w.K}-element N={w.N} "
+                      f"workload, dense FP64 numpy oracle, BLAS limited to 1 thread, {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--n", type=int, default=64, help="squares per side (64 -> 8192 triangles)")
+    ap.add_argument("--N", type=int, default=3)
+    ap.add_argument("--epb", type=int, default=0, help="elements per workgroup (0 = tuned default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
+    ap.add_argument("--no-graph", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this solver runs on a single MI355X "
+              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2005_02516_amd import workloads as wl
+    from paper_2005_02516_amd.binding import EsdgSwe
+
+    w = wl.config2(n=args.n, N=args.N)
+    Np, Nq, Nfq, Nh = dims(w.N)
+    dof = w.K * Np
+    print(f"# workload: K={w.K} N={w.N} Np={Np} DOF={dof} dt={w.dt:.4e}", file=sys.stderr, flush=True)
+
+    results = {}
+    states = {}
+    precs = [args.precision] + ([] if args.no_fp64 or args.precision == "fp64" else ["fp64"])
+    for prec in precs:
+        s = EsdgSwe([w], precision=prec, flux=w.flux, g=w.g, elems_per_block=args.epb, use_graph=not args.no_graph)
+        s.set_state(0, w.u_nodes)
+        s.step(w.dt, args.warmup)
+        s.sync()
+        ms = time_steps(s, w.dt, args.steps, torch)
+        s.sync()
+        states[prec] = s.get_state(0)
+        results[prec] = ms
+        print(f"# {prec}: {ms:.3f} ms for {args.steps} steps -> {ms / args.steps * 1e3:.2f} us/step, "
+              f"{ms / (5 * args.steps) * 1e3:.2f} us/stage", file=sys.stderr, flush=True)
+        s.close()
+
+    prec = args.precision
+    ms = results[prec]
+    t_stage = ms * 1e-3 / (5 * args.steps)
+    value = dof / t_stage
+    word = 4 if prec == "fp32" else 8
+    flops = alg_flops_per_elem(w.N) * w.K
+    byts = alg_bytes_per_elem(w.N, word) * w.K
+    achieved_tf = flops / t_stage / 1e12
+    achieved_gbs = byts / t_stage / 1e9
+    peak_alu = PEAK_FP32_TFLOPS if prec == "fp32" else PEAK_FP64_TFLOPS
+    frac_alu = achieved_tf / peak_alu
+    frac_hbm = achieved_gbs / PEAK_HBM_GBS
+    if frac_alu >= frac_hbm:
+        roof = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": peak_alu, "unit": "TFLOP/s",
+                "frac": round(frac_alu, 4), "traffic": None}
+    else:
+        roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(frac_hbm, 4), "traffic": None}
+    roof["kernel"] = "stage_kernel (fused RK stage: flux differencing + interface + lift + update + projection)"
+    roof["per_launch"] = {"alg_flops": flops, "alg_bytes": byts, "duration_us": round(t_stage * 1e6, 3),
+                          "duration_source": "HIP events over the timed graph replays / launches (includes launch gaps)",
+                          "other_bound": ({"hbm_GBs": round(achieved_gbs, 1), "frac": round(frac_hbm, 4)}
+                                          if roof["bound"] == "alu" else
+                                          {"alu_TFLOPs": round(achieved_tf, 3), "frac": round(frac_alu, 4)})}
+    out = {
+        "metric": "DOF-updates/s per RK stage at N=3; FP32/batched vs FP64 speedup at stated error",
+        "value": value,
+        "unit": "DOF-updates/s per RK stage",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"curved periodic lake at rest + Gaussian bump, {args.n}x{args.n}x2={w.K} triangles, "
+                               f"N={w.N} (Np={Np}, Nq={Nq}, Nfq={Nfq}), LF flux, LSRK4(5)",
+                   "K": w.K, "N": w.N, "DOF": dof, "precision": prec, "hip_graph": not args.no_graph},
+        "roofline": roof,
+    }
+    if "fp64" in results and prec != "fp64":
+        v64 = dof / (results["fp64"] * 1e-3 / (5 * args.steps))
+        a, b = states[prec], states["fp64"]
+        hn = float(np.linalg.norm(b[0]))
+        out["fp64_value"] = v64
+        out["speedup_vs_fp64"] = value / v64
+        out["rel_l2_vs_fp64_after_steps"] = {
+            "steps": args.steps + args.warmup,
+            "h": float(np.linalg.norm(a[0] - b[0]) / hn),
+            "hu_over_norm_h": float(np.linalg.norm(a[1] - b[1]) / hn),
+            "hv_over_norm_h": float(np.linalg.norm(a[2] - b[2]) / hn),
+            "hu": float(np.linalg.norm(a[1] - b[1]) / max(np.linalg.norm(b[1]), 1e-300)),
+            "hv": float(np.linalg.norm(a[2] - b[2]) / max(np.linalg.norm(b[2]), 1e-300)),
+        }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+/*
+ * esdg_swe.h -- C ABI of the MI355X (gfx950) library that evaluates the modal
+ * entropy-stable DG (ESDG) right-hand side of the 2D shallow water equations on
+ * curved triangles and advances it with the five-stage low-storage RK4.
+ *
+ * Method: Wu, Kubatko & Chan, "High-order entropy stable discontinuous Galerkin
+ * methods for the shallow water equations: curved triangular meshes and GPU
+ * acceleration", arXiv 2005.02516.
+ *
+ *   rhs = -(M_h^k)^{-1} V_h^T r_h, where r_h is the hybridized-node residual of the
+ *   semi-discrete form eq. (dgform) (Section 2.7): entropy projection (Section 2.5),
+ *   flux differencing with the hybridized SBP operators and the entropy-conservative
+ *   SWE flux on curved elements (Sections 2.3, 2.6, 2.7), bathymetry source, interface
+ *   flux with optional local Lax-Friedrichs penalty (Section 2.8), and the
+ *   per-element inverse curved mass matrix.  Time stepping: the 2N-storage
+ *   Carpenter-Kennedy RK4(5) named in Section 4.
+ *
+ * Conventions shared with the caller (they fix coefficient-level results):
+ *   - Reference triangle: counter-clockwise vertices v1=(-1,-1), v2=(1,-1), v3=(-1,1).
+ *   - Modal basis: orthonormal Dubiner basis
+ *       phi_ij(r,s) = sqrt(2) P~_i(a) P~_j^{(2i+1,0)}(b) (1-b)^i,
+ *       a = 2(1+r)/(1-s) - 1, b = s, P~ orthonormal Jacobi polynomials,
+ *     modes ordered "for i in 0..N: for j in 0..N-i".
+ *   - Quadrature: (N+1)^2-point Stroud collapsed rule (Gauss-Legendre x
+ *     Gauss-Jacobi(1,0), exact to degree 2N+1) and N+1 Gauss-Legendre points per face.
+ *   - Geometry / sampling nodes: order-N equispaced nodes listed
+ *       "for j in 0..N: for i in 0..N-j: (r,s) = (-1 + 2i/N, -1 + 2j/N)"
+ *     (node 0 = v1, node N = v2, last node = v3).  Each element is the
+ *     isoparametric degree-N map through its nodes.
+ *   - Np = (N+1)(N+2)/2.  State layout everywhere: [3][K][Np] (h, hu, hv), element-major
+ *     planes, modes fastest.
+ *
+ * Ownership: the caller owns every host array passed in and may free it once the call
+ * returns.  The caller owns the device workspace and the HIP stream given to
+ * esdg_swe_bind and must keep both alive until esdg_swe_destroy.  The library never
+ * allocates device memory: all its device arrays live in that workspace.
+ *
+ * Errors: every call returns an esdg_status; no C++ exception crosses this ABI.
+ * esdg_swe_last_error returns a message for the last failing call on a handle (or, with
+ * a NULL handle, for the last failing esdg_swe_init on this thread).
+ *
+ * Threading: a handle is not thread-safe; calls on one handle must be serialised.
+ */
+#ifndef ESDG_SWE_H
+#define ESDG_SWE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct esdg_swe esdg_swe;
+
+typedef enum {
+  ESDG_OK = 0,
+  ESDG_EINVAL = -1,     /* bad argument (null pointer, size, option out of range)         */
+  ESDG_EMESH = -2,      /* mesh rejected: J <= 0, unmatched periodic face node, ...        */
+  ESDG_ENOMEM = -3,     /* workspace smaller than esdg_swe_init asked for                  */
+  ESDG_EDEVICE = -4,    /* a HIP runtime call failed (message names it)                    */
+  ESDG_ENONPHYS = -5,   /* a kernel saw a non-finite value or a depth h~ <= 0              */
+  ESDG_ESTATE = -6      /* call out of order (e.g. step before bind or before set_state)   */
+} esdg_status;
+
+/* arithmetic of the bulk path */
+enum {
+  ESDG_FP64 = 0,        /* everything in double precision                                  */
+  ESDG_FP32 = 1,        /* state, operators, fluxes in float; the entropy <-> conservative
+                           variable maps and the diagnostics in double                     */
+  ESDG_FP32_BF16X3 = 2  /* as ESDG_FP32, with the projection and lift contractions done as
+                           three bf16 products (hi*hi + hi*lo + lo*hi) accumulated in float */
+};
+
+/* interface flux (Section 2.7 / 2.8) */
+enum {
+  ESDG_FLUX_EC = 0,     /* entropy-conservative flux, no dissipation                        */
+  ESDG_FLUX_LF = 1      /* plus local Lax-Friedrichs penalty on entropy-projected variables */
+};
+
+/* One independent shallow-water instance on a periodic box. */
+typedef struct {
+  int32_t N;            /* polynomial (and geometry) degree, 1..5                          */
+  int32_t K;            /* number of triangles, >= 1                                        */
+  const double *xg;     /* [K][Np] x of the equispaced geometry nodes (warped allowed)      */
+  const double *yg;     /* [K][Np] y of the same nodes; each element counter-clockwise      */
+  const double *b;      /* [K][Np] bathymetry sampled at the same nodes (C0 across faces for
+                           the well-balanced property); NULL means b = 0                     */
+  double Lx, Ly;        /* periods in x and y: every face must match a face of another
+                           element, possibly shifted by a multiple of (Lx, Ly)              */
+} esdg_swe_instance;
+
+typedef struct {
+  int32_t precision;        /* ESDG_FP64 | ESDG_FP32 | ESDG_FP32_BF16X3                      */
+  int32_t flux;             /* ESDG_FLUX_EC | ESDG_FLUX_LF                                   */
+  double g;                 /* gravitational constant, > 0                                    */
+  int32_t elems_per_block;  /* elements per workgroup; 0 = tuned default per N               */
+  int32_t use_graph;        /* nonzero: esdg_swe_step replays HIP graphs of its RK stages    */
+} esdg_swe_options;
+
+/* Plan a solver for n_inst independent instances (n_inst = 1 for a single run).  Builds,
+ * on the host in double precision, the reference operators of each degree, the
+ * isoparametric geometry, the periodic face connectivity and the inverse curved mass
+ * matrices (Sections 2.1-2.6).  Validates: 1 <= N <= 5, J > 0 at every quadrature node,
+ * every face node matched.  On success *out is a new handle and *workspace_bytes the
+ * device workspace size esdg_swe_bind needs.  No device call is made. */
+esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const esdg_swe_options *opt,
+                          esdg_swe **out, size_t *workspace_bytes);
+
+/* Attach a caller-owned device workspace (>= workspace_bytes, 256-byte aligned) and a
+ * HIP stream (hipStream_t as void*, NULL = default stream), then upload the operators
+ * and mesh data with asynchronous copies on that stream.  The handle keeps both. */
+esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *hip_stream);
+
+/* Set instance `inst`'s state from samples at its geometry nodes: u_nodes is host
+ * [3][K][Np] (h, hu, hv).  The library interpolates to modal coefficients, resets the RK
+ * register to zero and computes the entropy projection of the new state.  Synchronous. */
+esdg_status esdg_swe_set_state(esdg_swe *s, int32_t inst, const double *u_nodes);
+
+/* As esdg_swe_set_state, from modal coefficients uh (host [3][K][Np]). */
+esdg_status esdg_swe_set_state_modal(esdg_swe *s, int32_t inst, const double *uh);
+
+/* Copy instance `inst`'s modal state to the host as double [3][K][Np].  Synchronises the
+ * stream; returns ESDG_ENONPHYS if any kernel since the last check flagged a bad state. */
+esdg_status esdg_swe_get_state(esdg_swe *s, int32_t inst, double *uh);
+
+/* Device pointer to instance `inst`'s modal state ([3][K][Np], float for the FP32 modes,
+ * double for ESDG_FP64).  Valid until esdg_swe_destroy; reading it is ordered by the
+ * bound stream. */
+esdg_status esdg_swe_state_device(esdg_swe *s, int32_t inst, void **uh_dev);
+
+/* rhs_dev = du_h/dt of eq. (dgform) evaluated at state_dev for instance `inst`: both are
+ * device arrays [3][K][Np] in the library precision (float or double).  Asynchronous on
+ * the bound stream; does not touch the instance's own state.  state_dev and rhs_dev must
+ * not overlap. */
+esdg_status esdg_swe_rhs(esdg_swe *s, int32_t inst, const void *state_dev, void *rhs_dev);
+
+/* Advance every instance by nsteps LSRK4(5) steps (5 RHS evaluations each, Section 4).
+ * dt is a host array with one time step per instance.  Asynchronous on the bound stream:
+ * one kernel launch per RK stage for all instances together, replayed from HIP graphs
+ * when use_graph is set.  Non-physical states are reported by the next synchronising
+ * call (get_state, diagnostics, sync). */
+esdg_status esdg_swe_step(esdg_swe *s, const double *dt, int32_t nsteps);
+
+/* Per-instance FP64 diagnostics of the current state, out = host [n_inst][6]:
+ *   mass of h, hu, hv (sum_k 1^T W J V_q u_h), total entropy sum w J S(u_q) (Section 2.4),
+ *   entropy rate sum w J v(u_q).(V_q du/dt) (zero for the EC flux on periodic meshes,
+ *   <= 0 with LF), and the sum of the absolute values of the entropy-rate terms.
+ * Synchronises the stream. */
+esdg_status esdg_swe_diagnostics(esdg_swe *s, double *out);
+
+/* Wait for the bound stream; ESDG_ENONPHYS if a kernel flagged a bad state since the
+ * last check (the flag is then cleared). */
+esdg_status esdg_swe_sync(esdg_swe *s);
+
+/* Sizes of instance `inst`: out = {N, K, Np, Nq, Nfq, Nh}. */
+esdg_status esdg_swe_query(const esdg_swe *s, int32_t inst, int32_t *out6);
+
+/* Message for the last failing call on s (s may be NULL: last failing init on this thread). */
+const char *esdg_swe_last_error(const esdg_swe *s);
+
+/* Release host resources of the handle (HIP graphs included).  The workspace and stream
+ * remain the caller's.  NULL is ignored. */
+void esdg_swe_destroy(esdg_swe *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ESDG_SWE_H */

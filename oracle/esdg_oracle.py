@@ -342,6 +342,15 @@ class Discretization:
         rhs = (f_q * (ref.wq[None, :] * self.Jq)) @ ref.Vq
         return self.mh_solve(rhs)
 
+    def mh_solve_subset(self, r: np.ndarray, ks: np.ndarray) -> np.ndarray:
+        """Solve M_h^k x = r for the listed elements ks (r has shape [3, len(ks), Np])."""
+        L = self.Mh_chol[ks]
+        out = np.empty_like(r)
+        for c in range(r.shape[0]):
+            y = np.linalg.solve(L, r[c][..., None])[..., 0]
+            out[c] = np.linalg.solve(np.swapaxes(L, 1, 2), y[..., None])[..., 0]
+        return out
+
     def mh_solve(self, r: np.ndarray) -> np.ndarray:
         """Solve M_h^k x = r for every element (r has shape [..., K, Np])."""
         L = self.Mh_chol
@@ -434,7 +443,7 @@ class Oracle:
         ut = np.stack(conservative_from_entropy(vt[0], vt[1], vt[2], d.b_hyb, g))
         return ut, vh
 
-    def physical_Qh(self, ks: slice):
+    def physical_Qh(self, ks):
         """Q_h^{i,k}[m,n] = 1/2 sum_j (G_ij[m] + G_ij[n]) Qhat_h^j[m,n] (Section 2.6)."""
         d, ref = self.d, self.d.ref
         Qr, Qs = ref.Qh
@@ -444,48 +453,58 @@ class Oracle:
         Qy = op(d.ryJ[ks], d.syJ[ks])
         return Qx, Qy
 
-    def residual(self, uh: np.ndarray) -> np.ndarray:
+    def residual(self, uh: np.ndarray, elements: Optional[np.ndarray] = None) -> np.ndarray:
         """Hybridized-node residual r_h such that M_h du/dt = -V_h^T r_h.
 
         r_h = sum_i 2 (Q_h^{i,k} o F^i) 1 + [0; B^{i,k} (f_S^i(u~+, u~) - f^i(u~_f))] - S (+ LF penalty).
+        With ``elements`` (an index array) only those elements' rows are evaluated; the
+        result then has shape [3, len(elements), Nh].
         """
         d, ref, g = self.d, self.d.ref, self.d.g
         ut, _ = self.entropy_projection(uh)
-        K, Nq, Nh = d.K, ref.Nq, ref.Nh
-        r = np.zeros((3, K, Nh))
-        for k0 in range(0, K, self.chunk):
-            ks = slice(k0, min(K, k0 + self.chunk))
+        Nq, Nh = ref.Nq, ref.Nh
+        ks_all = np.arange(d.K) if elements is None else np.asarray(elements, dtype=np.int64)
+        r = np.zeros((3, ks_all.size, Nh))
+        for c0 in range(0, ks_all.size, self.chunk):
+            sel = slice(c0, min(ks_all.size, c0 + self.chunk))
+            ks = ks_all[sel]
             Qx, Qy = self.physical_Qh(ks)
             uL = tuple(ut[c, ks][:, :, None] for c in range(3))
             uR = tuple(ut[c, ks][:, None, :] for c in range(3))
             Fx, Fy = ec_flux(uL, uR, g)
             for c in range(3):
-                r[c, ks] += 2.0 * np.sum(Qx * Fx[c] + Qy * Fy[c], axis=2)
+                r[c, sel] += 2.0 * np.sum(Qx * Fx[c] + Qy * Fy[c], axis=2)
             # bathymetry source S = -g [0; diag(h~) Q^x b; diag(h~) Q^y b] moved to the left
             bt = d.b_hyb[ks]
-            r[1, ks] += g * ut[0, ks] * np.einsum("kmn,kn->km", Qx, bt)
-            r[2, ks] += g * ut[0, ks] * np.einsum("kmn,kn->km", Qy, bt)
+            r[1, sel] += g * ut[0, ks] * np.einsum("kmn,kn->km", Qx, bt)
+            r[2, sel] += g * ut[0, ks] * np.einsum("kmn,kn->km", Qy, bt)
         # interface terms on the face rows
-        uf = ut[:, :, Nq:]                                        # [3,K,Nfq]
-        up = uf.reshape(3, -1)[:, d.mapP.reshape(-1)].reshape(uf.shape)
+        uf = ut[:, ks_all, Nq:]                                   # [3,k,Nfq]
+        up = ut[:, :, Nq:].reshape(3, -1)[:, d.mapP[ks_all].reshape(-1)].reshape(uf.shape)
         fS_x, fS_y = ec_flux(tuple(up), tuple(uf), g)
         f_x, f_y = physical_flux(uf[0], uf[1], uf[2], g)
         wf = ref.wf[None, :]
+        nJx, nJy, sJ = d.nJx[ks_all], d.nJy[ks_all], d.sJ[ks_all]
         for c in range(3):
-            r[c, :, Nq:] += wf * (d.nJx * (fS_x[c] - f_x[c]) + d.nJy * (fS_y[c] - f_y[c]))
+            r[c, :, Nq:] += wf * (nJx * (fS_x[c] - f_x[c]) + nJy * (fS_y[c] - f_y[c]))
         if self.flux == "lf":
-            nx, ny = d.nJx / d.sJ, d.nJy / d.sJ
+            nx, ny = nJx / sJ, nJy / sJ
             def speed(u):
                 return np.abs((u[1] * nx + u[2] * ny) / u[0]) + np.sqrt(g * u[0])
             lam = np.maximum(speed(uf), speed(up))
             for c in range(3):
-                r[c, :, Nq:] -= wf * 0.5 * lam * d.sJ * (up[c] - uf[c])
+                r[c, :, Nq:] -= wf * 0.5 * lam * sJ * (up[c] - uf[c])
         return r
 
-    def rhs(self, uh: np.ndarray) -> np.ndarray:
-        """du_h/dt = -(M_h^k)^{-1} V_h^T r_h, solved with the Cholesky factors of M_h^k."""
-        r = self.residual(uh)
-        return -self.d.mh_solve(r @ self.d.ref.Vh)
+    def rhs(self, uh: np.ndarray, elements: Optional[np.ndarray] = None) -> np.ndarray:
+        """du_h/dt = -(M_h^k)^{-1} V_h^T r_h, solved with the Cholesky factors of M_h^k.
+
+        With ``elements``, only those elements (shape [3, len(elements), Np]).
+        """
+        r = self.residual(uh, elements)
+        if elements is None:
+            return -self.d.mh_solve(r @ self.d.ref.Vh)
+        return -self.d.mh_solve_subset(r @ self.d.ref.Vh, np.asarray(elements, dtype=np.int64))
 
 
 # ----------------------------------------------------------------------------------

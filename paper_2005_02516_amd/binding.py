@@ -1,0 +1,201 @@
+"""Thin ctypes binding of libesdg_swe.so (the C ABI in include/esdg_swe.h).
+
+Argument marshalling only: every step of the RHS and the RK update runs in the HIP
+kernels of the library.  PyTorch supplies the device workspace and the HIP stream.
+The module raises at load time if the library is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+from .build import library_path
+
+ESDG_OK, ESDG_EINVAL, ESDG_EMESH, ESDG_ENOMEM, ESDG_EDEVICE, ESDG_ENONPHYS, ESDG_ESTATE = 0, -1, -2, -3, -4, -5, -6
+ESDG_FP64, ESDG_FP32, ESDG_FP32_BF16X3 = 0, 1, 2
+ESDG_FLUX_EC, ESDG_FLUX_LF = 0, 1
+
+PRECISIONS = {"fp64": ESDG_FP64, "fp32": ESDG_FP32, "bf16x3": ESDG_FP32_BF16X3}
+FLUXES = {"ec": ESDG_FLUX_EC, "lf": ESDG_FLUX_LF}
+
+EXPORTED = [
+    "esdg_swe_init", "esdg_swe_bind", "esdg_swe_set_state", "esdg_swe_set_state_modal", "esdg_swe_get_state",
+    "esdg_swe_state_device", "esdg_swe_rhs", "esdg_swe_step", "esdg_swe_diagnostics", "esdg_swe_sync",
+    "esdg_swe_query", "esdg_swe_last_error", "esdg_swe_destroy",
+]
+
+
+class esdg_swe_instance(C.Structure):
+    _fields_ = [("N", C.c_int32), ("K", C.c_int32), ("xg", C.POINTER(C.c_double)), ("yg", C.POINTER(C.c_double)),
+                ("b", C.POINTER(C.c_double)), ("Lx", C.c_double), ("Ly", C.c_double)]
+
+
+class esdg_swe_options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("flux", C.c_int32), ("g", C.c_double),
+                ("elems_per_block", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class EsdgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"esdg status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None) -> C.CDLL:
+    """Load libesdg_swe.so and declare its signatures (no GPU needed for loading)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or library_path()
+    if not os.path.exists(p):
+        raise ImportError(f"{p} is missing: build it with `python -m paper_2005_02516_amd.build`")
+    lib = C.CDLL(p)
+    vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+    pdbl = C.POINTER(C.c_double)
+    lib.esdg_swe_init.argtypes = [i32, C.POINTER(esdg_swe_instance), C.POINTER(esdg_swe_options), C.POINTER(vp),
+                                  C.POINTER(C.c_size_t)]
+    lib.esdg_swe_bind.argtypes = [vp, vp, C.c_size_t, vp]
+    lib.esdg_swe_set_state.argtypes = [vp, i32, pdbl]
+    lib.esdg_swe_set_state_modal.argtypes = [vp, i32, pdbl]
+    lib.esdg_swe_get_state.argtypes = [vp, i32, pdbl]
+    lib.esdg_swe_state_device.argtypes = [vp, i32, C.POINTER(vp)]
+    lib.esdg_swe_rhs.argtypes = [vp, i32, vp, vp]
+    lib.esdg_swe_step.argtypes = [vp, pdbl, i32]
+    lib.esdg_swe_diagnostics.argtypes = [vp, pdbl]
+    lib.esdg_swe_sync.argtypes = [vp]
+    lib.esdg_swe_query.argtypes = [vp, i32, C.POINTER(i32)]
+    lib.esdg_swe_last_error.argtypes = [vp]
+    lib.esdg_swe_last_error.restype = C.c_char_p
+    lib.esdg_swe_destroy.argtypes = [vp]
+    lib.esdg_swe_destroy.restype = None
+    for name in EXPORTED:
+        if name not in ("esdg_swe_last_error", "esdg_swe_destroy"):
+            getattr(lib, name).restype = C.c_int32
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class EsdgSwe:
+    """One solver handle for n_inst instances, bound to a torch-allocated workspace."""
+
+    def __init__(self, instances: Sequence, precision: str = "fp64", flux: str = "lf", g: float = 1.0,
+                 elems_per_block: int = 0, use_graph: bool = True, device: str = "cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("EsdgSwe needs a GPU: the library has no CPU path")
+        self.lib = load_library()
+        self.torch = torch
+        self.device = torch.device(device)
+        self._keep = []
+        arr = (esdg_swe_instance * len(instances))()
+        for i, w in enumerate(instances):
+            xg = np.ascontiguousarray(w.xg, dtype=np.float64)
+            yg = np.ascontiguousarray(w.yg, dtype=np.float64)
+            b = np.ascontiguousarray(w.b_nodes, dtype=np.float64)
+            self._keep += [xg, yg, b]
+            arr[i] = esdg_swe_instance(w.N, w.K, _dptr(xg), _dptr(yg), _dptr(b), w.Lx, w.Ly)
+        opt = esdg_swe_options(PRECISIONS[precision], FLUXES[flux], float(g), int(elems_per_block), int(use_graph))
+        h = C.c_void_p()
+        nbytes = C.c_size_t()
+        st = self.lib.esdg_swe_init(len(instances), arr, C.byref(opt), C.byref(h), C.byref(nbytes))
+        if st != ESDG_OK:
+            raise EsdgError(st, self.lib.esdg_swe_last_error(None).decode())
+        self.h = h
+        self.n_inst = len(instances)
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self._check(self.lib.esdg_swe_bind(self.h, C.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                                           C.c_void_p(self.stream.cuda_stream)))
+        self.sizes = [self.query(i) for i in range(self.n_inst)]
+
+    # -- helpers -------------------------------------------------------------------
+    def _check(self, st: int):
+        if st != ESDG_OK:
+            raise EsdgError(st, self.lib.esdg_swe_last_error(self.h).decode())
+
+    def query(self, inst: int):
+        out = (C.c_int32 * 6)()
+        self._check(self.lib.esdg_swe_query(self.h, inst, out))
+        return dict(zip(["N", "K", "Np", "Nq", "Nfq", "Nh"], list(out)))
+
+    # -- C-ABI entry points (same names) ------------------------------------------
+    def esdg_swe_set_state(self, inst: int, u_nodes: np.ndarray):
+        u = np.ascontiguousarray(u_nodes, dtype=np.float64)
+        z = self.sizes[inst]
+        assert u.shape == (3, z["K"], z["Np"]), u.shape
+        self._check(self.lib.esdg_swe_set_state(self.h, inst, _dptr(u)))
+
+    def esdg_swe_set_state_modal(self, inst: int, uh: np.ndarray):
+        u = np.ascontiguousarray(uh, dtype=np.float64)
+        z = self.sizes[inst]
+        assert u.shape == (3, z["K"], z["Np"]), u.shape
+        self._check(self.lib.esdg_swe_set_state_modal(self.h, inst, _dptr(u)))
+
+    def esdg_swe_get_state(self, inst: int) -> np.ndarray:
+        z = self.sizes[inst]
+        out = np.empty((3, z["K"], z["Np"]), dtype=np.float64)
+        self._check(self.lib.esdg_swe_get_state(self.h, inst, _dptr(out)))
+        return out
+
+    def esdg_swe_state_device(self, inst: int):
+        """torch view of the instance state in the workspace ([3][K][Np], library precision)."""
+        p = C.c_void_p()
+        self._check(self.lib.esdg_swe_state_device(self.h, inst, C.byref(p)))
+        z = self.sizes[inst]
+        off = p.value - self.workspace.data_ptr()
+        nbytes = 3 * z["K"] * z["Np"] * (8 if self.dtype == self.torch.float64 else 4)
+        return self.workspace[off:off + nbytes].view(self.dtype).view(3, z["K"], z["Np"])
+
+    def esdg_swe_rhs(self, inst: int, state, rhs):
+        z = self.sizes[inst]
+        for t in (state, rhs):
+            assert t.is_cuda and t.dtype == self.dtype and t.is_contiguous() and tuple(t.shape) == (3, z["K"], z["Np"])
+        self._check(self.lib.esdg_swe_rhs(self.h, inst, C.c_void_p(state.data_ptr()), C.c_void_p(rhs.data_ptr())))
+
+    def esdg_swe_step(self, dt, nsteps: int):
+        d = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (self.n_inst,)))
+        self._check(self.lib.esdg_swe_step(self.h, _dptr(d), int(nsteps)))
+
+    def esdg_swe_diagnostics(self) -> np.ndarray:
+        out = np.empty((self.n_inst, 6), dtype=np.float64)
+        self._check(self.lib.esdg_swe_diagnostics(self.h, _dptr(out)))
+        return out
+
+    def esdg_swe_sync(self):
+        self._check(self.lib.esdg_swe_sync(self.h))
+
+    # short aliases
+    set_state = esdg_swe_set_state
+    set_state_modal = esdg_swe_set_state_modal
+    get_state = esdg_swe_get_state
+    state_device = esdg_swe_state_device
+    rhs = esdg_swe_rhs
+    step = esdg_swe_step
+    diagnostics = esdg_swe_diagnostics
+    sync = esdg_swe_sync
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.stream.synchronize()
+            self.lib.esdg_swe_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

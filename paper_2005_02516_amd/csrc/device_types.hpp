@@ -1,0 +1,79 @@
+// Types shared by the HIP kernels and the host runtime of the ESDG shallow-water library.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace esdg {
+
+constexpr int kMaxN = 5;
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64s)
+constexpr int kNodeRec = 11;       // per hybrid node in LDS: hu/2 hv/2 u/2 v/2 gh/2 dH rxJ sxJ ryJ syJ h
+
+__host__ __device__ constexpr int dim_Np(int N) { return (N + 1) * (N + 2) / 2; }
+__host__ __device__ constexpr int dim_Nq(int N) { return (N + 1) * (N + 1); }
+__host__ __device__ constexpr int dim_Nfq(int N) { return 3 * (N + 1); }
+__host__ __device__ constexpr int dim_Nh(int N) { return dim_Nq(N) + dim_Nfq(N); }
+
+// Reference-operator block of degree N, stored contiguously in the bulk precision:
+// Vh [Nh][Np] | Sr [Nq][Nh] | Ss [Nq][Nh] | wf [Nfq] | nr [Nfq] | ns [Nfq].
+__host__ __device__ constexpr int ref_words(int N) {
+  return dim_Nh(N) * dim_Np(N) + 2 * dim_Nq(N) * dim_Nh(N) + 3 * dim_Nfq(N);
+}
+
+// Words (of the bulk precision) of LDS a workgroup needs for E elements of degree N.
+// Layout: ref block | node records [E][Nh][kNodeRec] (reused for projected values
+// [3][E][Nq]) | residual [3][E][Nh] | A [3][E][Np] | B [3][E][Np].
+__host__ __device__ constexpr int lds_words(int N, int E) {
+  return ref_words(N) + E * dim_Nh(N) * kNodeRec + 3 * E * dim_Nh(N) + 6 * E * dim_Np(N);
+}
+
+// One instance as the kernels see it (device pointers into the bound workspace).
+struct InstDesc {
+  int32_t N, K, flux, pad0;
+  double g, Href, dt, pad1;
+  void *uh;            // [3][K][Np] modal state
+  void *du;            // [3][K][Np] LSRK register
+  void *ut[3];         // [4][K][Nh] entropy-projected h~, u~, v~, H~ - Href (two stage buffers + rhs scratch)
+  const void *geo;     // [4][K][Nh] rxJ, sxJ, ryJ, syJ
+  const void *wJq;     // [K][Nq] w_q J
+  const void *Minv;    // [K][Np][Np]
+  const double *bq;    // [K][Nq]
+  const double *bh;    // [K][Nh]
+  const int32_t *mapP; // [K][Nfq] index k'*Nh + Nq + f' of the neighbour node
+  const void *ref;     // reference-operator block for this N
+  void *rhs_scratch;   // [3][K][Np] used by the diagnostics
+};
+
+// A contiguous range of elements of one instance, processed by one workgroup.
+struct Tile {
+  int32_t inst, k0, ne, pad;
+};
+
+enum StageMode : int32_t {
+  kProject = 0,   // state -> entropy-projected values (ut[out])
+  kRhs = 1,       // ut[in] -> rhs (no update)
+  kStage = 2      // ut[in] -> rhs -> LSRK update of uh, du -> project new uh to ut[out]
+};
+
+struct StageArgs {
+  const InstDesc *desc;
+  const Tile *tiles;
+  int32_t ntiles;
+  int32_t mode;
+  int32_t in_buf, out_buf;
+  double rk_a, rk_b;
+  const void *ext_state;  // kProject: read this state instead of desc.uh (when non-null)
+  void *ext_rhs;          // kRhs: write here
+  int32_t *flag;          // set nonzero when a non-physical value is seen
+};
+
+struct DiagArgs {
+  const InstDesc *desc;
+  const Tile *tiles;
+  int32_t ntiles;
+  int32_t pad;
+  double *partials;       // [ntiles][6]
+};
+
+}  // namespace esdg

@@ -1,0 +1,544 @@
+// C-ABI runtime of the ESDG shallow-water library: planning (host FP64 setup), the
+// device workspace layout, uploads, RK-stage launches, HIP-graph replay and diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/esdg_swe.h"
+#include "device_types.hpp"
+#include "host_setup.hpp"
+
+namespace esdg {
+hipError_t set_stage_lds_limit(bool fp64, size_t lds_bytes);
+hipError_t launch_stage(bool fp64, const StageArgs &a, int grid, size_t lds_bytes, hipStream_t stream);
+hipError_t launch_diag(bool fp64, const DiagArgs &a, hipStream_t stream);
+}  // namespace esdg
+
+using namespace esdg;
+
+namespace {
+
+// Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage coefficients.
+const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+const double kRkB[5] = {1432997174477.0 / 9575080441904.0, 5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+
+thread_local std::string g_init_error;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Default elements per workgroup: as many as keep E*Nh <= 512 and LDS <= 48 KiB.
+int default_epb(int N, size_t word) {
+  int best = 1;
+  for (int E = 1; E <= 64; E *= 2) {
+    if (E * dim_Nh(N) > 512) break;
+    if (size_t(lds_words(N, E)) * word > 48 * 1024) break;
+    best = E;
+  }
+  return best;
+}
+
+struct Offsets {
+  size_t uh, du, ut[3], geo, wJq, Minv, bq, bh, mapP, rhs;
+};
+
+}  // namespace
+
+struct esdg_swe {
+  int n_inst = 0;
+  esdg_swe_options opt{};
+  bool fp64 = true;
+  size_t word = 8;
+  std::map<int, RefElem> refs;
+  std::vector<InstanceHost> host;
+  std::vector<Offsets> off;
+  std::map<int, size_t> ref_off;
+  size_t tiles_off = 0, desc_off = 0, flag_off = 0, partial_off = 0;
+  size_t ws_bytes = 0;
+  std::map<int, int> epb;          // elements per workgroup per N
+  size_t lds_bytes = 0;
+  std::vector<Tile> tiles;
+  std::vector<int> tile_begin, tile_count;
+  std::vector<InstDesc> desc;
+  // binding
+  unsigned char *ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  std::vector<bool> state_set;
+  int parity = 0;                  // which ut buffer holds the projection of the current state
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (steps, start parity) -> exec
+  std::string err;
+
+  ~esdg_swe() {
+    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  }
+  template <typename T>
+  T *dev(size_t o) const { return reinterpret_cast<T *>(ws + o); }
+  esdg_status fail(esdg_status st, const std::string &m) {
+    err = m;
+    return st;
+  }
+  esdg_status hip_fail(hipError_t e, const char *what) {
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return ESDG_EDEVICE;
+  }
+};
+
+namespace {
+
+// Convert doubles to the bulk precision into a byte buffer.
+std::vector<unsigned char> to_bulk(const std::vector<double> &v, bool fp64) {
+  std::vector<unsigned char> out(v.size() * (fp64 ? 8 : 4));
+  if (fp64) {
+    std::memcpy(out.data(), v.data(), out.size());
+  } else {
+    float *f = reinterpret_cast<float *>(out.data());
+    for (size_t i = 0; i < v.size(); ++i) f[i] = float(v[i]);
+  }
+  return out;
+}
+
+std::vector<double> ref_block(const RefElem &R) {
+  std::vector<double> b;
+  b.reserve(ref_words(R.N));
+  b.insert(b.end(), R.Vh.a.begin(), R.Vh.a.end());
+  b.insert(b.end(), R.Sr.a.begin(), R.Sr.a.end());
+  b.insert(b.end(), R.Ss.a.begin(), R.Ss.a.end());
+  b.insert(b.end(), R.wf.begin(), R.wf.end());
+  b.insert(b.end(), R.nr.begin(), R.nr.end());
+  b.insert(b.end(), R.ns.begin(), R.ns.end());
+  return b;
+}
+
+esdg_status upload(esdg_swe *s, size_t off, const void *src, size_t bytes) {
+  hipError_t e = hipMemcpyAsync(s->ws + off, src, bytes, hipMemcpyHostToDevice, s->stream);
+  if (e != hipSuccess) return s->hip_fail(e, "hipMemcpyAsync (upload)");
+  return ESDG_OK;
+}
+
+esdg_status launch(esdg_swe *s, const StageArgs &a, int ntiles) {
+  hipError_t e = launch_stage(s->fp64, a, ntiles, s->lds_bytes, s->stream);
+  if (e != hipSuccess) return s->hip_fail(e, "stage kernel launch");
+  return ESDG_OK;
+}
+
+StageArgs base_args(esdg_swe *s, int inst) {
+  StageArgs a{};
+  a.desc = s->dev<InstDesc>(s->desc_off);
+  if (inst < 0) {
+    a.tiles = s->dev<Tile>(s->tiles_off);
+    a.ntiles = int(s->tiles.size());
+  } else {
+    a.tiles = s->dev<Tile>(s->tiles_off) + s->tile_begin[inst];
+    a.ntiles = s->tile_count[inst];
+  }
+  a.flag = s->dev<int32_t>(s->flag_off);
+  return a;
+}
+
+esdg_status check_flag(esdg_swe *s) {
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return s->hip_fail(e, "hipStreamSynchronize");
+  int32_t flag = 0;
+  e = hipMemcpy(&flag, s->dev<int32_t>(s->flag_off), sizeof flag, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return s->hip_fail(e, "hipMemcpy (flag)");
+  if (flag) {
+    int32_t zero = 0;
+    (void)hipMemcpy(s->dev<int32_t>(s->flag_off), &zero, sizeof zero, hipMemcpyHostToDevice);
+    return s->fail(ESDG_ENONPHYS, "a kernel saw a non-finite value or a depth h~ <= 0");
+  }
+  return ESDG_OK;
+}
+
+esdg_status set_modal(esdg_swe *s, int inst, const std::vector<double> &uh) {
+  const InstanceHost &H = s->host[inst];
+  const RefElem &R = s->refs.at(H.N);
+  const size_t n = size_t(3) * H.K * R.Np;
+  // reference level for the pressure term: mean of h + b over volume nodes
+  double sum = 0.0, wsum = 0.0;
+  for (int k = 0; k < H.K; ++k)
+    for (int q = 0; q < R.Nq; ++q) {
+      double hq = 0.0;
+      for (int j = 0; j < R.Np; ++j) hq += R.Vh(q, j) * uh[size_t(k) * R.Np + j];
+      const double w = H.wJq[size_t(k) * R.Nq + q];
+      sum += w * (hq + H.bq[size_t(k) * R.Nq + q]);
+      wsum += w;
+    }
+  s->desc[inst].Href = sum / wsum;
+  auto bulk = to_bulk(uh, s->fp64);
+  esdg_status st = upload(s, s->off[inst].uh, bulk.data(), bulk.size());
+  if (st) return st;
+  hipError_t e = hipMemsetAsync(s->ws + s->off[inst].du, 0, n * s->word, s->stream);
+  if (e != hipSuccess) return s->hip_fail(e, "hipMemsetAsync (du)");
+  st = upload(s, s->desc_off + inst * sizeof(InstDesc), &s->desc[inst], sizeof(InstDesc));
+  if (st) return st;
+  StageArgs a = base_args(s, inst);
+  a.mode = kProject;
+  a.out_buf = s->parity;
+  st = launch(s, a, a.ntiles);
+  if (st) return st;
+  s->state_set[inst] = true;
+  return check_flag(s);
+}
+
+}  // namespace
+
+extern "C" {
+
+esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const esdg_swe_options *opt, esdg_swe **out,
+                          size_t *workspace_bytes) {
+  g_init_error.clear();
+  if (!out || !workspace_bytes || !inst || !opt || n_inst < 1) {
+    g_init_error = "esdg_swe_init: null argument or n_inst < 1";
+    return ESDG_EINVAL;
+  }
+  *out = nullptr;
+  if (opt->precision < ESDG_FP64 || opt->precision > ESDG_FP32_BF16X3 || opt->flux < 0 || opt->flux > 1 ||
+      !(opt->g > 0.0) || opt->elems_per_block < 0 || opt->elems_per_block > 64) {
+    g_init_error = "esdg_swe_init: option out of range";
+    return ESDG_EINVAL;
+  }
+  if (opt->precision == ESDG_FP32_BF16X3) {
+    g_init_error = "esdg_swe_init: ESDG_FP32_BF16X3 is not available in this build";
+    return ESDG_EINVAL;
+  }
+  std::unique_ptr<esdg_swe> s(new esdg_swe());
+  s->n_inst = n_inst;
+  s->opt = *opt;
+  s->fp64 = opt->precision == ESDG_FP64;
+  s->word = s->fp64 ? 8 : 4;
+  s->host.resize(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    const esdg_swe_instance &I = inst[i];
+    if (I.N < 1 || I.N > kMaxN || I.K < 1 || !I.xg || !I.yg || !(I.Lx > 0) || !(I.Ly > 0)) {
+      g_init_error = "esdg_swe_init: instance " + std::to_string(i) + ": bad N, K, pointers or periods";
+      return ESDG_EINVAL;
+    }
+    if (!s->refs.count(I.N)) {
+      s->refs[I.N] = build_ref(I.N);
+      std::string chk = check_ref(s->refs[I.N], 1e-12);
+      if (!chk.empty()) {
+        g_init_error = chk;
+        return ESDG_EINVAL;
+      }
+    }
+    std::string m = build_instance(s->refs[I.N], I.K, I.xg, I.yg, I.b, I.Lx, I.Ly, s->host[i]);
+    if (!m.empty()) {
+      g_init_error = "instance " + std::to_string(i) + ": " + m;
+      return ESDG_EMESH;
+    }
+    if (size_t(I.K) * dim_Nh(I.N) >= size_t(1) << 31) {
+      g_init_error = "instance " + std::to_string(i) + ": K * Nh exceeds the 32-bit face index";
+      return ESDG_EINVAL;
+    }
+  }
+  // elements per workgroup and LDS
+  size_t lds = 0;
+  for (auto &kv : s->refs) {
+    const int N = kv.first;
+    int E = opt->elems_per_block ? opt->elems_per_block : default_epb(N, s->word);
+    s->epb[N] = E;
+    lds = std::max(lds, size_t(lds_words(N, E)) * s->word);
+  }
+  if (lds > 160 * 1024) {
+    g_init_error = "esdg_swe_init: elems_per_block needs more than 160 KiB of LDS";
+    return ESDG_EINVAL;
+  }
+  s->lds_bytes = lds;
+  // tiles
+  s->tile_begin.resize(n_inst);
+  s->tile_count.resize(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    const int E = s->epb[inst[i].N];
+    s->tile_begin[i] = int(s->tiles.size());
+    for (int k0 = 0; k0 < inst[i].K; k0 += E) s->tiles.push_back(Tile{i, k0, std::min(E, inst[i].K - k0), 0});
+    s->tile_count[i] = int(s->tiles.size()) - s->tile_begin[i];
+  }
+  // workspace layout
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align256(o + bytes);
+    return r;
+  };
+  for (auto &kv : s->refs) s->ref_off[kv.first] = take(size_t(ref_words(kv.first)) * s->word);
+  s->off.resize(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    const int N = inst[i].N, K = inst[i].K;
+    const size_t Np = dim_Np(N), Nq = dim_Nq(N), Nh = dim_Nh(N), Nfq = dim_Nfq(N), w = s->word;
+    Offsets &f = s->off[i];
+    f.uh = take(3 * K * Np * w);
+    f.du = take(3 * K * Np * w);
+    for (int b = 0; b < 3; ++b) f.ut[b] = take(4 * K * Nh * w);
+    f.geo = take(4 * K * Nh * w);
+    f.wJq = take(K * Nq * w);
+    f.Minv = take(K * Np * Np * w);
+    f.bq = take(K * Nq * 8);
+    f.bh = take(K * Nh * 8);
+    f.mapP = take(K * Nfq * 4);
+    f.rhs = take(3 * K * Np * w);
+  }
+  s->tiles_off = take(s->tiles.size() * sizeof(Tile));
+  s->desc_off = take(n_inst * sizeof(InstDesc));
+  s->flag_off = take(256);
+  s->partial_off = take(s->tiles.size() * 6 * sizeof(double));
+  s->ws_bytes = o;
+  s->desc.resize(n_inst);
+  s->state_set.assign(n_inst, false);
+  *workspace_bytes = s->ws_bytes;
+  *out = s.release();
+  return ESDG_OK;
+}
+
+esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *hip_stream) {
+  if (!s || !dev_workspace) return s ? s->fail(ESDG_EINVAL, "bind: null workspace") : ESDG_EINVAL;
+  if (bytes < s->ws_bytes) return s->fail(ESDG_ENOMEM, "bind: workspace smaller than esdg_swe_init asked for");
+  if (reinterpret_cast<uintptr_t>(dev_workspace) % 256) return s->fail(ESDG_EINVAL, "bind: workspace not 256-byte aligned");
+  s->ws = static_cast<unsigned char *>(dev_workspace);
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  if (s->lds_bytes > 64 * 1024) {
+    hipError_t e = set_stage_lds_limit(s->fp64, s->lds_bytes);
+    if (e != hipSuccess) return s->hip_fail(e, "hipFuncSetAttribute (LDS)");
+  }
+  esdg_status st;
+  // host staging buffers stay alive until the stream is synchronised below
+  std::vector<std::vector<unsigned char>> keep;
+  for (auto &kv : s->refs) {
+    keep.push_back(to_bulk(ref_block(kv.second), s->fp64));
+    if ((st = upload(s, s->ref_off[kv.first], keep.back().data(), keep.back().size()))) return st;
+  }
+  for (int i = 0; i < s->n_inst; ++i) {
+    const InstanceHost &H = s->host[i];
+    const Offsets &f = s->off[i];
+    keep.push_back(to_bulk(H.geo, s->fp64));
+    if ((st = upload(s, f.geo, keep.back().data(), keep.back().size()))) return st;
+    keep.push_back(to_bulk(H.wJq, s->fp64));
+    if ((st = upload(s, f.wJq, keep.back().data(), keep.back().size()))) return st;
+    keep.push_back(to_bulk(H.Minv, s->fp64));
+    if ((st = upload(s, f.Minv, keep.back().data(), keep.back().size()))) return st;
+    if ((st = upload(s, f.bq, H.bq.data(), H.bq.size() * 8))) return st;
+    if ((st = upload(s, f.bh, H.bh.data(), H.bh.size() * 8))) return st;
+    if ((st = upload(s, f.mapP, H.mapP.data(), H.mapP.size() * 4))) return st;
+    InstDesc &d = s->desc[i];
+    d.N = H.N;
+    d.K = H.K;
+    d.flux = s->opt.flux;
+    d.g = s->opt.g;
+    d.Href = 0.0;
+    d.dt = 0.0;
+    d.uh = s->ws + f.uh;
+    d.du = s->ws + f.du;
+    for (int b = 0; b < 3; ++b) d.ut[b] = s->ws + f.ut[b];
+    d.geo = s->ws + f.geo;
+    d.wJq = s->ws + f.wJq;
+    d.Minv = s->ws + f.Minv;
+    d.bq = s->dev<double>(f.bq);
+    d.bh = s->dev<double>(f.bh);
+    d.mapP = s->dev<int32_t>(f.mapP);
+    d.ref = s->ws + s->ref_off[H.N];
+    d.rhs_scratch = s->ws + f.rhs;
+  }
+  if ((st = upload(s, s->desc_off, s->desc.data(), s->desc.size() * sizeof(InstDesc)))) return st;
+  if ((st = upload(s, s->tiles_off, s->tiles.data(), s->tiles.size() * sizeof(Tile)))) return st;
+  hipError_t e = hipMemsetAsync(s->ws + s->flag_off, 0, 256, s->stream);
+  if (e != hipSuccess) return s->hip_fail(e, "hipMemsetAsync (flag)");
+  e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return s->hip_fail(e, "hipStreamSynchronize (bind)");
+  s->bound = true;
+  return ESDG_OK;
+}
+
+esdg_status esdg_swe_set_state(esdg_swe *s, int32_t inst, const double *u_nodes) {
+  if (!s) return ESDG_EINVAL;
+  if (!s->bound) return s->fail(ESDG_ESTATE, "set_state before bind");
+  if (inst < 0 || inst >= s->n_inst || !u_nodes) return s->fail(ESDG_EINVAL, "set_state: bad instance or null");
+  const InstanceHost &H = s->host[inst];
+  const RefElem &R = s->refs.at(H.N);
+  const size_t plane = size_t(H.K) * R.Np;
+  std::vector<double> uh(3 * plane);
+  for (int c = 0; c < 3; ++c) nodes_to_modes(R, H.K, u_nodes + c * plane, uh.data() + c * plane);
+  return set_modal(s, inst, uh);
+}
+
+esdg_status esdg_swe_set_state_modal(esdg_swe *s, int32_t inst, const double *uh) {
+  if (!s) return ESDG_EINVAL;
+  if (!s->bound) return s->fail(ESDG_ESTATE, "set_state_modal before bind");
+  if (inst < 0 || inst >= s->n_inst || !uh) return s->fail(ESDG_EINVAL, "set_state_modal: bad instance or null");
+  const InstanceHost &H = s->host[inst];
+  std::vector<double> v(uh, uh + size_t(3) * H.K * dim_Np(H.N));
+  return set_modal(s, inst, v);
+}
+
+esdg_status esdg_swe_get_state(esdg_swe *s, int32_t inst, double *uh) {
+  if (!s) return ESDG_EINVAL;
+  if (!s->bound || inst < 0 || inst >= s->n_inst || !uh) return s->fail(ESDG_EINVAL, "get_state: bad arguments");
+  esdg_status st = check_flag(s);
+  const InstanceHost &H = s->host[inst];
+  const size_t n = size_t(3) * H.K * dim_Np(H.N);
+  std::vector<unsigned char> buf(n * s->word);
+  hipError_t e = hipMemcpy(buf.data(), s->ws + s->off[inst].uh, buf.size(), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return s->hip_fail(e, "hipMemcpy (get_state)");
+  if (s->fp64)
+    std::memcpy(uh, buf.data(), buf.size());
+  else
+    for (size_t i = 0; i < n; ++i) uh[i] = reinterpret_cast<const float *>(buf.data())[i];
+  return st;
+}
+
+esdg_status esdg_swe_state_device(esdg_swe *s, int32_t inst, void **uh_dev) {
+  if (!s) return ESDG_EINVAL;
+  if (!s->bound || inst < 0 || inst >= s->n_inst || !uh_dev) return s->fail(ESDG_EINVAL, "state_device: bad arguments");
+  *uh_dev = s->ws + s->off[inst].uh;
+  return ESDG_OK;
+}
+
+esdg_status esdg_swe_rhs(esdg_swe *s, int32_t inst, const void *state_dev, void *rhs_dev) {
+  if (!s) return ESDG_EINVAL;
+  if (!s->bound) return s->fail(ESDG_ESTATE, "rhs before bind");
+  if (inst < 0 || inst >= s->n_inst || !state_dev || !rhs_dev) return s->fail(ESDG_EINVAL, "rhs: bad arguments");
+  if (!s->state_set[inst]) return s->fail(ESDG_ESTATE, "rhs: set_state first (defines the pressure reference level)");
+  const size_t bytes = size_t(3) * s->host[inst].K * dim_Np(s->host[inst].N) * s->word;
+  const char *a0 = static_cast<const char *>(state_dev), *b0 = static_cast<const char *>(rhs_dev);
+  if (a0 < b0 + bytes && b0 < a0 + bytes) return s->fail(ESDG_EINVAL, "rhs: state and rhs overlap");
+  StageArgs a = base_args(s, inst);
+  a.mode = kProject;
+  a.ext_state = state_dev;
+  a.out_buf = 2;
+  esdg_status st = launch(s, a, a.ntiles);
+  if (st) return st;
+  a.mode = kRhs;
+  a.in_buf = 2;
+  a.ext_state = nullptr;
+  a.ext_rhs = rhs_dev;
+  return launch(s, a, a.ntiles);
+}
+
+static esdg_status run_steps_direct(esdg_swe *s, int nsteps) {
+  for (int n = 0; n < nsteps; ++n)
+    for (int st = 0; st < 5; ++st) {
+      StageArgs a = base_args(s, -1);
+      a.mode = kStage;
+      a.in_buf = s->parity;
+      a.out_buf = 1 - s->parity;
+      a.rk_a = kRkA[st];
+      a.rk_b = kRkB[st];
+      esdg_status r = launch(s, a, a.ntiles);
+      if (r) return r;
+      s->parity = 1 - s->parity;
+    }
+  return ESDG_OK;
+}
+
+esdg_status esdg_swe_step(esdg_swe *s, const double *dt, int32_t nsteps) {
+  if (!s) return ESDG_EINVAL;
+  if (!s->bound) return s->fail(ESDG_ESTATE, "step before bind");
+  if (!dt || nsteps < 0) return s->fail(ESDG_EINVAL, "step: null dt or negative nsteps");
+  for (int i = 0; i < s->n_inst; ++i) {
+    if (!s->state_set[i]) return s->fail(ESDG_ESTATE, "step: instance " + std::to_string(i) + " has no state");
+    if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return s->fail(ESDG_EINVAL, "step: dt must be positive and finite");
+  }
+  bool changed = false;
+  for (int i = 0; i < s->n_inst; ++i)
+    if (s->desc[i].dt != dt[i]) {
+      s->desc[i].dt = dt[i];
+      changed = true;
+    }
+  if (changed) {
+    esdg_status st = upload(s, s->desc_off, s->desc.data(), s->desc.size() * sizeof(InstDesc));
+    if (st) return st;
+  }
+  if (nsteps == 0) return ESDG_OK;
+  if (!s->opt.use_graph || s->stream == nullptr) return run_steps_direct(s, nsteps);
+  // graphs of an even number of steps keep the stage-buffer parity; replay them
+  const int chunk = std::min(nsteps - nsteps % 2, 20);
+  int done = 0;
+  if (chunk >= 2) {
+    auto key = std::make_pair(chunk, s->parity);
+    hipGraphExec_t exec = nullptr;
+    auto it = s->graphs.find(key);
+    if (it == s->graphs.end()) {
+      hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return s->hip_fail(e, "hipStreamBeginCapture");
+      const int p0 = s->parity;
+      esdg_status st = run_steps_direct(s, chunk);
+      hipGraph_t graph = nullptr;
+      e = hipStreamEndCapture(s->stream, &graph);
+      s->parity = p0;
+      if (st) return st;
+      if (e != hipSuccess) return s->hip_fail(e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return s->hip_fail(e, "hipGraphInstantiate");
+      s->graphs[key] = exec;
+    } else {
+      exec = it->second;
+    }
+    while (nsteps - done >= chunk) {
+      hipError_t e = hipGraphLaunch(exec, s->stream);
+      if (e != hipSuccess) return s->hip_fail(e, "hipGraphLaunch");
+      done += chunk;
+    }
+  }
+  return run_steps_direct(s, nsteps - done);
+}
+
+esdg_status esdg_swe_diagnostics(esdg_swe *s, double *out) {
+  if (!s) return ESDG_EINVAL;
+  if (!s->bound || !out) return s->fail(ESDG_EINVAL, "diagnostics: bad arguments");
+  for (int i = 0; i < s->n_inst; ++i) {
+    if (!s->state_set[i]) return s->fail(ESDG_ESTATE, "diagnostics: instance without state");
+    esdg_status st = esdg_swe_rhs(s, i, s->ws + s->off[i].uh, s->ws + s->off[i].rhs);
+    if (st) return st;
+  }
+  DiagArgs a{};
+  a.desc = s->dev<InstDesc>(s->desc_off);
+  a.tiles = s->dev<Tile>(s->tiles_off);
+  a.ntiles = int(s->tiles.size());
+  a.partials = s->dev<double>(s->partial_off);
+  hipError_t e = launch_diag(s->fp64, a, s->stream);
+  if (e != hipSuccess) return s->hip_fail(e, "diag kernel launch");
+  esdg_status st = check_flag(s);
+  std::vector<double> part(s->tiles.size() * 6);
+  e = hipMemcpy(part.data(), s->dev<double>(s->partial_off), part.size() * 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return s->hip_fail(e, "hipMemcpy (diagnostics)");
+  for (int i = 0; i < s->n_inst; ++i) {
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int t = s->tile_begin[i]; t < s->tile_begin[i] + s->tile_count[i]; ++t)
+      for (int c = 0; c < 6; ++c) acc[c] += part[size_t(t) * 6 + c];
+    for (int c = 0; c < 6; ++c) out[i * 6 + c] = acc[c];
+  }
+  return st;
+}
+
+esdg_status esdg_swe_sync(esdg_swe *s) {
+  if (!s) return ESDG_EINVAL;
+  if (!s->bound) return s->fail(ESDG_ESTATE, "sync before bind");
+  return check_flag(s);
+}
+
+esdg_status esdg_swe_query(const esdg_swe *s, int32_t inst, int32_t *out6) {
+  if (!s || !out6 || inst < 0 || inst >= s->n_inst) return ESDG_EINVAL;
+  const int N = s->host[inst].N;
+  out6[0] = N;
+  out6[1] = s->host[inst].K;
+  out6[2] = dim_Np(N);
+  out6[3] = dim_Nq(N);
+  out6[4] = dim_Nfq(N);
+  out6[5] = dim_Nh(N);
+  return ESDG_OK;
+}
+
+const char *esdg_swe_last_error(const esdg_swe *s) { return s ? s->err.c_str() : g_init_error.c_str(); }
+
+void esdg_swe_destroy(esdg_swe *s) { delete s; }
+
+}  // extern "C"

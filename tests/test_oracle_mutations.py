@@ -96,8 +96,8 @@ def test_source_sign_flip_caught(monkeypatch):
     """Adding the bathymetry source with the wrong sign breaks the lake at rest."""
     real = O.Oracle.residual
 
-    def flipped(self, uh):
-        r = real(self, uh)
+    def flipped(self, uh, elements=None):
+        r = real(self, uh, elements)
         ut, _ = self.entropy_projection(uh)
         Qx, Qy = self.physical_Qh(slice(0, self.d.K))
         g = self.d.g
