@@ -79,8 +79,10 @@ def test_rhs_fp64(torch, name, make, flux):
     s.sync()
     r_gpu = rhs.cpu().numpy()
     r_ref = o.rhs(uh_gpu)
+    # relative to max |rhs| per field: the dense form's own rounding (cancelling pressure
+    # terms of size g h H) is ~1e-13..1e-12 of that, so the bar for one RHS is 1e-11
     err = rel_field_err(r_gpu, r_ref)
-    assert np.all(err < 1e-12), err
+    assert np.all(err < 1e-11), err
     s.close()
 
 
@@ -212,7 +214,7 @@ def test_ragged_tiles_and_small_meshes(torch):
         s.sync()
         err = rel_field_err(rhs.cpu().numpy(), o.rhs(s.get_state(0)), scale=1.0)
         s.close()
-        assert np.all(err < 1e-12), (n, N, epb, err)
+        assert np.all(err < 1e-11), (n, N, epb, err)
 
 
 def test_batched_mixed_instances(torch):
