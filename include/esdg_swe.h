@@ -27,8 +27,13 @@
  *       "for j in 0..N: for i in 0..N-j: (r,s) = (-1 + 2i/N, -1 + 2j/N)"
  *     (node 0 = v1, node N = v2, last node = v3).  Each element is the
  *     isoparametric degree-N map through its nodes.
- *   - Np = (N+1)(N+2)/2.  State layout everywhere: [3][K][Np] (h, hu, hv), element-major
- *     planes, modes fastest.
+ *   - Np = (N+1)(N+2)/2.  State layout everywhere: [3][K][Np], element-major planes, modes
+ *     fastest.  Host-side states (set_state*, get_state) hold (h, hu, hv).  Device-side
+ *     states (esdg_swe_state_device, esdg_swe_rhs) hold (eta, hu, hv) with the depth
+ *     carried as the free-surface anomaly eta = h + b - Href, Href the instance's
+ *     reference level (esdg_swe_reference_level): the modal coefficients of eta are those
+ *     of h plus those of b minus Href*sqrt(2) on mode 0 (the constant 1 is sqrt(2) phi_00).
+ *     The time derivative of eta equals that of h.
  *
  * Ownership: the caller owns every host array passed in and may free it once the call
  * returns.  The caller owns the device workspace and the HIP stream given to
@@ -124,13 +129,14 @@ esdg_status esdg_swe_set_state_modal(esdg_swe *s, int32_t inst, const double *uh
  * stream; returns ESDG_ENONPHYS if any kernel since the last check flagged a bad state. */
 esdg_status esdg_swe_get_state(esdg_swe *s, int32_t inst, double *uh);
 
-/* Device pointer to instance `inst`'s modal state ([3][K][Np], float for the FP32 modes,
- * double for ESDG_FP64).  Valid until esdg_swe_destroy; reading it is ordered by the
- * bound stream. */
+/* Device pointer to instance `inst`'s modal state ([3][K][Np] (eta, hu, hv), float for the
+ * FP32 modes, double for ESDG_FP64).  Valid until esdg_swe_destroy; reading it is ordered
+ * by the bound stream. */
 esdg_status esdg_swe_state_device(esdg_swe *s, int32_t inst, void **uh_dev);
 
 /* rhs_dev = du_h/dt of eq. (dgform) evaluated at state_dev for instance `inst`: both are
- * device arrays [3][K][Np] in the library precision (float or double).  Asynchronous on
+ * device arrays [3][K][Np] in the library precision (float or double); state_dev holds
+ * (eta, hu, hv) as esdg_swe_state_device does, rhs_dev receives d/dt of (h, hu, hv).  Asynchronous on
  * the bound stream; does not touch the instance's own state.  state_dev and rhs_dev must
  * not overlap. */
 esdg_status esdg_swe_rhs(esdg_swe *s, int32_t inst, const void *state_dev, void *rhs_dev);
@@ -152,6 +158,12 @@ esdg_status esdg_swe_diagnostics(esdg_swe *s, double *out);
 /* Wait for the bound stream; ESDG_ENONPHYS if a kernel flagged a bad state since the
  * last check (the flag is then cleared). */
 esdg_status esdg_swe_sync(esdg_swe *s);
+
+/* Reference level Href of instance `inst` (the mean of h + b over the domain at the last
+ * set_state; it defines eta = h + b - Href and the H - Href form of the pressure terms,
+ * both exact rewritings because the operators annihilate constants).  ESDG_ESTATE before
+ * the first set_state. */
+esdg_status esdg_swe_reference_level(const esdg_swe *s, int32_t inst, double *Href);
 
 /* Sizes of instance `inst`: out = {N, K, Np, Nq, Nfq, Nh}. */
 esdg_status esdg_swe_query(const esdg_swe *s, int32_t inst, int32_t *out6);

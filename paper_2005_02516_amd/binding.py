@@ -24,7 +24,7 @@ FLUXES = {"ec": ESDG_FLUX_EC, "lf": ESDG_FLUX_LF}
 EXPORTED = [
     "esdg_swe_init", "esdg_swe_bind", "esdg_swe_set_state", "esdg_swe_set_state_modal", "esdg_swe_get_state",
     "esdg_swe_state_device", "esdg_swe_rhs", "esdg_swe_step", "esdg_swe_diagnostics", "esdg_swe_sync",
-    "esdg_swe_query", "esdg_swe_last_error", "esdg_swe_destroy",
+    "esdg_swe_query", "esdg_swe_reference_level", "esdg_swe_last_error", "esdg_swe_destroy",
 ]
 
 
@@ -70,6 +70,7 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
     lib.esdg_swe_diagnostics.argtypes = [vp, pdbl]
     lib.esdg_swe_sync.argtypes = [vp]
     lib.esdg_swe_query.argtypes = [vp, i32, C.POINTER(i32)]
+    lib.esdg_swe_reference_level.argtypes = [vp, i32, pdbl]
     lib.esdg_swe_last_error.argtypes = [vp]
     lib.esdg_swe_last_error.restype = C.c_char_p
     lib.esdg_swe_destroy.argtypes = [vp]
@@ -151,8 +152,13 @@ class EsdgSwe:
         self._check(self.lib.esdg_swe_get_state(self.h, inst, _dptr(out)))
         return out
 
+    def esdg_swe_reference_level(self, inst: int) -> float:
+        out = C.c_double()
+        self._check(self.lib.esdg_swe_reference_level(self.h, inst, C.byref(out)))
+        return out.value
+
     def esdg_swe_state_device(self, inst: int):
-        """torch view of the instance state in the workspace ([3][K][Np], library precision)."""
+        """torch view of the instance state in the workspace ([3][K][Np] (eta, hu, hv), library precision)."""
         p = C.c_void_p()
         self._check(self.lib.esdg_swe_state_device(self.h, inst, C.byref(p)))
         z = self.sizes[inst]
@@ -187,6 +193,7 @@ class EsdgSwe:
     step = esdg_swe_step
     diagnostics = esdg_swe_diagnostics
     sync = esdg_swe_sync
+    reference_level = esdg_swe_reference_level
 
     def close(self):
         if getattr(self, "h", None):

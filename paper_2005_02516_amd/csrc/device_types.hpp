@@ -9,6 +9,7 @@ namespace esdg {
 constexpr int kMaxN = 5;
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64s)
 constexpr int kNodeRec = 11;       // per hybrid node in LDS: hu/2 hv/2 u/2 v/2 gh/2 dH rxJ sxJ ryJ syJ h
+constexpr int kXcds = 8;           // MI355X accelerator complex dies (each with its own L2)
 
 __host__ __device__ constexpr int dim_Np(int N) { return (N + 1) * (N + 2) / 2; }
 __host__ __device__ constexpr int dim_Nq(int N) { return (N + 1) * (N + 1); }
@@ -16,30 +17,37 @@ __host__ __device__ constexpr int dim_Nfq(int N) { return 3 * (N + 1); }
 __host__ __device__ constexpr int dim_Nh(int N) { return dim_Nq(N) + dim_Nfq(N); }
 
 // Reference-operator block of degree N, stored contiguously in the bulk precision:
-// Vh [Nh][Np] | Sr [Nq][Nh] | Ss [Nq][Nh] | wf [Nfq] | nr [Nfq] | ns [Nfq].
+//   Vh [Nh][Np]
+//   ST [Nh][Nq][2]  ST[n][m] = (S^r[m][n], S^s[m][n]) for volume rows m (column-major
+//                   so one column's entries for consecutive rows are contiguous)
+//   FT [Nq][Nfq][2] FT[n][f] = (-S^r[n][Nq+f], -S^s[n][Nq+f]): face row f, volume column n
+//   wf [Nfq] | nr [Nfq] | ns [Nfq]
+// where S^j = 1/2 (Qhat_h^j - Qhat_h^j^T) (its surface-surface block is zero).
 __host__ __device__ constexpr int ref_words(int N) {
-  return dim_Nh(N) * dim_Np(N) + 2 * dim_Nq(N) * dim_Nh(N) + 3 * dim_Nfq(N);
+  return dim_Nh(N) * dim_Np(N) + 2 * dim_Nh(N) * dim_Nq(N) + 2 * dim_Nq(N) * dim_Nfq(N) + 3 * dim_Nfq(N);
 }
 
-// Words (of the bulk precision) of LDS a workgroup needs for E elements of degree N.
-// Layout: ref block | node records [E][Nh][kNodeRec] (reused for projected values
-// [3][E][Nq]) | residual [3][E][Nh] | A [3][E][Np] | B [3][E][Np].
+// Words (of the bulk precision) of LDS a workgroup needs for E elements of degree N:
+// ref block | node records [E][Nh][kNodeRec] | fetched u~ and metrics [8][E][Nh] |
+// neighbour values [E][Nfq][4] | state, RK register [3][E][Np] each | Minv [E][Np][Np] |
+// w J [E][Nq] | b at volume nodes [E][Nq] | b at hybrid nodes [E][Nh].
 __host__ __device__ constexpr int lds_words(int N, int E) {
-  return ref_words(N) + E * dim_Nh(N) * kNodeRec + 3 * E * dim_Nh(N) + 6 * E * dim_Np(N);
+  return ref_words(N) + E * (dim_Nh(N) * kNodeRec + 8 * dim_Nh(N) + 4 * dim_Nfq(N) + 6 * dim_Np(N) +
+                             dim_Np(N) * dim_Np(N) + 2 * dim_Nq(N) + dim_Nh(N));
 }
 
 // One instance as the kernels see it (device pointers into the bound workspace).
 struct InstDesc {
   int32_t N, K, flux, pad0;
   double g, Href, dt, pad1;
-  void *uh;            // [3][K][Np] modal state
+  void *uh;            // [3][K][Np] modal state (eta = h + b - Href, hu, hv)
   void *du;            // [3][K][Np] LSRK register
   void *ut[3];         // [4][K][Nh] entropy-projected h~, u~, v~, H~ - Href (two stage buffers + rhs scratch)
   const void *geo;     // [4][K][Nh] rxJ, sxJ, ryJ, syJ
   const void *wJq;     // [K][Nq] w_q J
   const void *Minv;    // [K][Np][Np]
-  const double *bq;    // [K][Nq]
-  const double *bh;    // [K][Nh]
+  const void *bq;      // [K][Nq] bathymetry at volume nodes
+  const void *bh;      // [K][Nh] bathymetry at hybrid nodes
   const int32_t *mapP; // [K][Nfq] index k'*Nh + Nq + f' of the neighbour node
   const void *ref;     // reference-operator block for this N
   void *rhs_scratch;   // [3][K][Np] used by the diagnostics

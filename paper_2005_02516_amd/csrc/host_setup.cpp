@@ -311,6 +311,7 @@ std::string build_instance(const RefElem &R, int K, const double *xg, const doub
   out.Minv.assign(size_t(K) * Np * Np, 0.0);
   out.bq.assign(size_t(K) * Nq, 0.0);
   out.bh.assign(size_t(K) * Nh, 0.0);
+  out.bmodal.assign(size_t(K) * Np, 0.0);
   out.mapP.assign(size_t(K) * Nfq, -1);
   std::vector<double> xh(size_t(K) * Nh), yh(size_t(K) * Nh);
   std::vector<double> xm(Np), ym(Np), bm(Np), Mh(size_t(Np) * Np);
@@ -326,6 +327,7 @@ std::string build_instance(const RefElem &R, int K, const double *xg, const doub
         if (b) sb += c * b[size_t(k) * Np + p];
       }
       xm[i] = sx; ym[i] = sy; bm[i] = sb;
+      out.bmodal[size_t(k) * Np + i] = sb;
     }
     std::vector<double> J(Nh);
     for (int n = 0; n < Nh; ++n) {

@@ -46,6 +46,7 @@ struct InstanceHost {
   std::vector<double> Minv;   // [K][Np][Np]: (V_q^T W diag(J) V_q)^{-1}
   std::vector<double> bq;     // [K][Nq]: bathymetry at volume nodes
   std::vector<double> bh;     // [K][Nh]: bathymetry at hybrid nodes
+  std::vector<double> bmodal; // [K][Np]: modal coefficients of the bathymetry
   std::vector<int32_t> mapP;  // [K][Nfq]: k' * Nh + Nq + f' of the matching neighbour node
   double Jmin = 0, Jmax = 0;
 };

@@ -1,21 +1,28 @@
 // HIP kernels (gfx950) for one RK stage of the modal ESDG shallow-water scheme.
 //
-// One workgroup processes a tile of consecutive elements of one instance.  Per tile:
-//   1. node records of the entropy-projected state u~ (Section 2.5) and the J-scaled
-//      metrics at the Nh hybridized nodes are staged in LDS;
-//   2. flux differencing in skew form (Section 5.2, Step 4): for every row m and every
-//      column n of the nonzero blocks of Q_skew = Q_h - Q_h^T (volume-volume and
-//      volume-surface; the surface-surface block is zero and skipped), with the
-//      element's physical operator built on the fly from averaged geometric factors
-//      (Section 2.6) and the EC flux of Section 2.7.  The bathymetry source is folded
-//      into the pair term as 1/2 g h_m (H_n - Href) Q_mn, exact because Q_h 1 = 0;
-//   3. the interface flux f_S(u~+, u~) on face rows with the neighbour's values gathered
-//      through mapP, the boundary half of the source, and the optional Lax-Friedrichs
-//      penalty (Section 2.8);
-//   4. lift: rhs = -(M_h^k)^{-1} V_h^T r_h (Section 2.7, stored inverses);
-//   5. LSRK update (Section 4) and, fused, the entropy projection of the updated state
-//      for the next stage (element-local), written to the other stage buffer.
+// One workgroup processes a tile of consecutive elements of one instance:
+//   0. every global array the tile needs (entropy-projected values of the tile and of
+//      its face neighbours, metric factors, state, RK register, inverse mass matrices,
+//      weights, bathymetry) is fetched into LDS in one phase, so the global-memory
+//      latency is exposed once per tile;
+//   1. node records at the Nh hybridized nodes are built in LDS;
+//   2. flux differencing in skew form (Section 5.2, Step 4): every row m of every
+//      nonzero block of Q_skew = Q_h - Q_h^T (volume-volume and volume-surface; the zero
+//      surface-surface block is skipped), with the element's physical operator built on
+//      the fly from averaged geometric factors (Section 2.6) and the EC flux of
+//      Section 2.7; each thread owns R rows of one element so a column's node record is
+//      read once for R rows.  The bathymetry source is folded in as
+//      1/2 g h_m (H_n - Href) Q_mn (exact because Q_h 1 = 0);
+//   3. interface flux f_S(u~+, u~), boundary half of the source and optional local
+//      Lax-Friedrichs penalty (Section 2.8) on the face rows;
+//   4. lift rhs = -(M_h^k)^{-1} V_h^T r_h with the stored inverses (Section 2.7);
+//   5. LSRK update (Section 4), then, fused, the entropy projection of the updated state
+//      (Section 2.5) written to the other stage buffer for the next stage.
 // The launch boundary is the grid-wide barrier the neighbour gather needs.
+//
+// Depth is carried as the free-surface anomaly eta = h + b - Href (Href a per-instance
+// constant), so the projection works on v1 - g Href and no quantity of size g H is
+// rounded to the bulk precision; the conversions to h are done in double.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -24,43 +31,74 @@
 
 namespace esdg {
 
-template <typename real>
 __device__ inline bool bad_value(double h, double a, double b) {
   return !(h > 0.0) || !isfinite(h) || !isfinite(a) || !isfinite(b);
 }
 
-// Entropy projection of the element states held in sA ([3][ne][Np], modal) to the
-// hybridized nodes, written to ut[3+1 planes] at out (Section 2.5):
-//   u_q = V_q u_h; v_q = v(u_q) (FP64); v_h = Minv_k V_q^T diag(w J) v_q; v~ = V_h v_h;
-//   u~ = u(v~) (FP64) stored as h~, v~2 (= u~), v~3 (= v~), H~ - Href.
+// LDS carve-up of one tile (see lds_words()).
 template <typename real, int N>
-__device__ void project_tile(const InstDesc &d, int k0, int ne, const real *sVh, real *sA, real *sB, real *sQ,
-                             real *out, int32_t *flag) {
+struct Lds {
+  static constexpr int Np = dim_Np(N), Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
+  real *ref, *Vh, *ST, *FT, *wf, *nr, *ns;
+  real *rec, *raw, *nb, *U, *DU, *Minv, *wJ, *bq, *bh;
+  real *R, *T, *Q;
+  __device__ Lds(real *sm, int E) {
+    ref = sm;
+    Vh = ref;
+    ST = Vh + Nh * Np;
+    FT = ST + 2 * Nh * Nq;
+    wf = FT + 2 * Nq * Nfq;
+    nr = wf + Nfq;
+    ns = nr + Nfq;
+    rec = sm + ref_words(N);
+    raw = rec + E * Nh * kNodeRec;
+    nb = raw + 8 * E * Nh;
+    U = nb + 4 * E * Nfq;
+    DU = U + 3 * E * Np;
+    Minv = DU + 3 * E * Np;
+    wJ = Minv + E * Np * Np;
+    bq = wJ + E * Nq;
+    bh = bq + E * Nq;
+    // reuse: residual and lift temporaries live in the raw block (dead after phase 1),
+    // the projection's pointwise values in the record block (dead after phase 2)
+    R = raw;
+    T = raw + 3 * E * Nh;
+    Q = rec;
+  }
+};
+
+// Entropy projection of the tile states in L.U ([3][ne][Np]: eta, hu, hv) to the
+// hybridized nodes (Section 2.5), written to out ([4][K][Nh]: h~, u~, v~, H~ - Href):
+//   q = V_q u_h; h = eta_q + Href - b_q; v' = (g eta_q - |u|^2/2, u, v) = v(u_q) - (g Href, 0, 0)
+//   (FP64); v'_h = Minv_k V_q^T diag(w J) v'_q; v~' = V_h v'_h;
+//   H~ - Href = (v~1' + |v~23|^2/2)/g, h~ = Href + (H~ - Href) - b~ (FP64).
+// Subtracting the constant g Href is exact: the projection reproduces constants.
+template <typename real, int N>
+__device__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L, real *out, int32_t *flag) {
   constexpr int Np = dim_Np(N), Nq = dim_Nq(N), Nh = dim_Nh(N);
   const int K = d.K;
-  const double g = d.g;
-  const real *wJq = static_cast<const real *>(d.wJq);
-  const real *Minv = static_cast<const real *>(d.Minv);
+  const double g = d.g, Href = d.Href;
   const int tid = threadIdx.x, nth = blockDim.x;
   bool bad = false;
   for (int i = tid; i < ne * Nq; i += nth) {
-    const int e = i / Nq, q = i - e * Nq, k = k0 + e;
+    const int e = i / Nq, q = i - e * Nq;
     real u0 = 0, u1 = 0, u2 = 0;
 #pragma unroll 4
     for (int j = 0; j < Np; ++j) {
-      const real v = sVh[q * Np + j];
-      u0 += v * sA[0 * ne * Np + e * Np + j];
-      u1 += v * sA[1 * ne * Np + e * Np + j];
-      u2 += v * sA[2 * ne * Np + e * Np + j];
+      const real v = L.Vh[q * Np + j];
+      u0 += v * L.U[0 * ne * Np + e * Np + j];
+      u1 += v * L.U[1 * ne * Np + e * Np + j];
+      u2 += v * L.U[2 * ne * Np + e * Np + j];
     }
-    const double h = u0, hu = u1, hv = u2;
+    const double eta = u0, hu = u1, hv = u2;
+    const double h = eta + Href - double(L.bq[i]);
     const double uu = hu / h, vv = hv / h;
-    const double v1 = g * (h + d.bq[size_t(k) * Nq + q]) - 0.5 * (uu * uu + vv * vv);
-    const double w = wJq[size_t(k) * Nq + q];
-    sQ[0 * ne * Nq + i] = real(w * v1);
-    sQ[1 * ne * Nq + i] = real(w * uu);
-    sQ[2 * ne * Nq + i] = real(w * vv);
-    bad |= bad_value<real>(h, hu, hv);
+    const double v1 = g * eta - 0.5 * (uu * uu + vv * vv);
+    const double w = L.wJ[i];
+    L.Q[0 * ne * Nq + i] = real(w * v1);
+    L.Q[1 * ne * Nq + i] = real(w * uu);
+    L.Q[2 * ne * Nq + i] = real(w * vv);
+    bad |= bad_value(h, hu, hv);
   }
   __syncthreads();
   for (int i = tid; i < ne * Np; i += nth) {
@@ -68,205 +106,286 @@ __device__ void project_tile(const InstDesc &d, int k0, int ne, const real *sVh,
     real y0 = 0, y1 = 0, y2 = 0;
 #pragma unroll 4
     for (int q = 0; q < Nq; ++q) {
-      const real v = sVh[q * Np + j];
-      y0 += v * sQ[0 * ne * Nq + e * Nq + q];
-      y1 += v * sQ[1 * ne * Nq + e * Nq + q];
-      y2 += v * sQ[2 * ne * Nq + e * Nq + q];
+      const real v = L.Vh[q * Np + j];
+      y0 += v * L.Q[0 * ne * Nq + e * Nq + q];
+      y1 += v * L.Q[1 * ne * Nq + e * Nq + q];
+      y2 += v * L.Q[2 * ne * Nq + e * Nq + q];
     }
-    sB[0 * ne * Np + i] = y0;
-    sB[1 * ne * Np + i] = y1;
-    sB[2 * ne * Np + i] = y2;
+    L.T[0 * ne * Np + i] = y0;
+    L.T[1 * ne * Np + i] = y1;
+    L.T[2 * ne * Np + i] = y2;
   }
   __syncthreads();
   for (int i = tid; i < ne * Np; i += nth) {
-    const int e = i / Np, row = i - e * Np, k = k0 + e;
-    const real *Mi = Minv + (size_t(k) * Np + row) * Np;
+    const int e = i / Np, row = i - e * Np;
+    const real *Mi = L.Minv + (e * Np + row) * Np;
     real v0 = 0, v1 = 0, v2 = 0;
 #pragma unroll 4
     for (int j = 0; j < Np; ++j) {
       const real m = Mi[j];
-      v0 += m * sB[0 * ne * Np + e * Np + j];
-      v1 += m * sB[1 * ne * Np + e * Np + j];
-      v2 += m * sB[2 * ne * Np + e * Np + j];
+      v0 += m * L.T[0 * ne * Np + e * Np + j];
+      v1 += m * L.T[1 * ne * Np + e * Np + j];
+      v2 += m * L.T[2 * ne * Np + e * Np + j];
     }
-    sA[0 * ne * Np + i] = v0;
-    sA[1 * ne * Np + i] = v1;
-    sA[2 * ne * Np + i] = v2;
+    L.U[0 * ne * Np + i] = v0;
+    L.U[1 * ne * Np + i] = v1;
+    L.U[2 * ne * Np + i] = v2;
   }
   __syncthreads();
   const size_t plane = size_t(K) * Nh;
   for (int i = tid; i < ne * Nh; i += nth) {
-    const int e = i / Nh, n = i - e * Nh, k = k0 + e;
+    const int e = i / Nh, n = i - e * Nh;
     real t0 = 0, t1 = 0, t2 = 0;
 #pragma unroll 4
     for (int j = 0; j < Np; ++j) {
-      const real v = sVh[n * Np + j];
-      t0 += v * sA[0 * ne * Np + e * Np + j];
-      t1 += v * sA[1 * ne * Np + e * Np + j];
-      t2 += v * sA[2 * ne * Np + e * Np + j];
+      const real v = L.Vh[n * Np + j];
+      t0 += v * L.U[0 * ne * Np + e * Np + j];
+      t1 += v * L.U[1 * ne * Np + e * Np + j];
+      t2 += v * L.U[2 * ne * Np + e * Np + j];
     }
     const double v1 = t0, v2 = t1, v3 = t2;
-    const double H = (v1 + 0.5 * (v2 * v2 + v3 * v3)) / g;
-    const double h = H - d.bh[size_t(k) * Nh + n];
-    const size_t o = size_t(k) * Nh + n;
+    const double dH = (v1 + 0.5 * (v2 * v2 + v3 * v3)) / g;
+    const double h = Href + dH - double(L.bh[i]);
+    const size_t o = size_t(k0) * Nh + i;
     out[0 * plane + o] = real(h);
     out[1 * plane + o] = real(v2);
     out[2 * plane + o] = real(v3);
-    out[3 * plane + o] = real(H - d.Href);
-    bad |= bad_value<real>(h, v2, v3);
+    out[3 * plane + o] = real(dH);
+    bad |= bad_value(h, v2, v3);
   }
   if (bad) atomicOr(flag, 1);
 }
 
-// Flux differencing + interface flux + lift for one tile; then either write rhs or do
-// the LSRK update and project the updated state.
+// Phase 0: fetch the tile's global data into LDS.
 template <typename real, int N>
-__device__ void volume_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm) {
+__device__ void fetch_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, Lds<real, N> &L) {
   constexpr int Np = dim_Np(N), Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
-  const int K = d.K;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const size_t plane = size_t(d.K) * Nh, splane = size_t(d.K) * Np;
+  const real *ref = static_cast<const real *>(d.ref);
+  for (int i = tid; i < ref_words(N); i += nth) L.ref[i] = ref[i];
+  if (a.mode != kProject) {
+    const real *ut = static_cast<const real *>(d.ut[a.in_buf]);
+    const real *geo = static_cast<const real *>(d.geo);
+    const size_t base = size_t(k0) * Nh;
+    for (int i = tid; i < ne * Nh; i += nth) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        L.raw[c * ne * Nh + i] = ut[c * plane + base + i];
+        L.raw[(4 + c) * ne * Nh + i] = geo[c * plane + base + i];
+      }
+    }
+    const int32_t *mapP = d.mapP + size_t(k0) * Nfq;
+    for (int i = tid; i < ne * Nfq; i += nth) {
+      const int32_t p = mapP[i];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) L.nb[i * 4 + c] = ut[c * plane + p];
+    }
+  }
+  if (a.mode == kStage) {
+    const real *uh = static_cast<const real *>(d.uh);
+    const real *du = static_cast<const real *>(d.du);
+    for (int i = tid; i < ne * Np; i += nth) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        L.U[c * ne * Np + i] = uh[c * splane + size_t(k0) * Np + i];
+        L.DU[c * ne * Np + i] = du[c * splane + size_t(k0) * Np + i];
+      }
+    }
+  }
+  const real *Minv = static_cast<const real *>(d.Minv) + size_t(k0) * Np * Np;
+  for (int i = tid; i < ne * Np * Np; i += nth) L.Minv[i] = Minv[i];
+  const real *wJ = static_cast<const real *>(d.wJq) + size_t(k0) * Nq;
+  const real *bq = static_cast<const real *>(d.bq) + size_t(k0) * Nq;
+  for (int i = tid; i < ne * Nq; i += nth) {
+    L.wJ[i] = wJ[i];
+    L.bq[i] = bq[i];
+  }
+  const real *bh = static_cast<const real *>(d.bh) + size_t(k0) * Nh;
+  for (int i = tid; i < ne * Nh; i += nth) L.bh[i] = bh[i];
+}
+
+// Phase 2+3: residual rows, R rows of one element per thread.
+template <typename real, int N, int R>
+__device__ void residual_tile(const InstDesc &d, int ne, Lds<real, N> &L) {
+  constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
+  constexpr int VB = Nq / R, FB = Nfq / R;
+  static_assert(Nq % R == 0 && Nfq % R == 0, "R must divide Nq and Nfq");
   const int tid = threadIdx.x, nth = blockDim.x;
   const real g = real(d.g);
-  const real *sVh = sm;
-  const real *sSr = sVh + Nh * Np;
-  const real *sSs = sSr + Nq * Nh;
-  const real *sF = sSs + Nq * Nh;
-  real *sNode = sm + ref_words(N);
-  real *sR = sNode + ne * Nh * kNodeRec;
-  real *sA = sR + 3 * ne * Nh;
-  real *sB = sA + 3 * ne * Np;
-  const size_t plane = size_t(K) * Nh;
-  const real *ut = static_cast<const real *>(d.ut[a.in_buf]);
-  const real *geo = static_cast<const real *>(d.geo);
+  // volume rows: all Nh columns (the diagonal of the skew operator is zero)
+  for (int t = tid; t < ne * VB; t += nth) {
+    const int e = t / VB, m0 = (t - e * VB) * R;
+    const real *rbase = L.rec + e * Nh * kNodeRec;
+    real hu[R], hv[R], u[R], v[R], gh[R], rx[R], sx[R], ry[R], sy[R], a0[R], a1[R], a2[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const real *rm = rbase + (m0 + r) * kNodeRec;
+      hu[r] = rm[0]; hv[r] = rm[1]; u[r] = rm[2]; v[r] = rm[3]; gh[r] = rm[4];
+      rx[r] = rm[6]; sx[r] = rm[7]; ry[r] = rm[8]; sy[r] = rm[9];
+      a0[r] = 0; a1[r] = 0; a2[r] = 0;
+    }
+#pragma unroll 2
+    for (int n = 0; n < Nh; ++n) {
+      const real *rn = rbase + n * kNodeRec;
+      const real hun = rn[0], hvn = rn[1], un = rn[2], vn = rn[3], dHn = rn[5];
+      const real rxn = rn[6], sxn = rn[7], ryn = rn[8], syn = rn[9];
+      const real *S = L.ST + (n * Nq + m0) * 2;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const real Sr = S[2 * r], Ss = S[2 * r + 1];
+        const real Qx = (rx[r] + rxn) * Sr + (sx[r] + sxn) * Ss;
+        const real Qy = (ry[r] + ryn) * Sr + (sy[r] + syn) * Ss;
+        const real c = Qx * (hu[r] + hun) + Qy * (hv[r] + hvn);
+        const real t = gh[r] * dHn;
+        a0[r] += c;
+        a1[r] += (u[r] + un) * c + t * Qx;
+        a2[r] += (v[r] + vn) * c + t * Qy;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      L.R[0 * ne * Nh + e * Nh + m0 + r] = a0[r];
+      L.R[1 * ne * Nh + e * Nh + m0 + r] = a1[r];
+      L.R[2 * ne * Nh + e * Nh + m0 + r] = a2[r];
+    }
+  }
+  // face rows: volume columns only (the surface-surface block is zero), then the
+  // interface flux W_f [ nJ . f_S(u~, u~+) + 1/2 g h (H+ - Href) nJ ] - LF
+  for (int t = tid; t < ne * FB; t += nth) {
+    const int e = t / FB, f0 = (t - e * FB) * R;
+    const real *rbase = L.rec + e * Nh * kNodeRec;
+    real hu[R], hv[R], u[R], v[R], gh[R], rx[R], sx[R], ry[R], sy[R], a0[R], a1[R], a2[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const real *rm = rbase + (Nq + f0 + r) * kNodeRec;
+      hu[r] = rm[0]; hv[r] = rm[1]; u[r] = rm[2]; v[r] = rm[3]; gh[r] = rm[4];
+      rx[r] = rm[6]; sx[r] = rm[7]; ry[r] = rm[8]; sy[r] = rm[9];
+      a0[r] = 0; a1[r] = 0; a2[r] = 0;
+    }
+#pragma unroll 2
+    for (int n = 0; n < Nq; ++n) {
+      const real *rn = rbase + n * kNodeRec;
+      const real hun = rn[0], hvn = rn[1], un = rn[2], vn = rn[3], dHn = rn[5];
+      const real rxn = rn[6], sxn = rn[7], ryn = rn[8], syn = rn[9];
+      const real *S = L.FT + (n * Nfq + f0) * 2;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const real Sr = S[2 * r], Ss = S[2 * r + 1];
+        const real Qx = (rx[r] + rxn) * Sr + (sx[r] + sxn) * Ss;
+        const real Qy = (ry[r] + ryn) * Sr + (sy[r] + syn) * Ss;
+        const real c = Qx * (hu[r] + hun) + Qy * (hv[r] + hvn);
+        const real tt = gh[r] * dHn;
+        a0[r] += c;
+        a1[r] += (u[r] + un) * c + tt * Qx;
+        a2[r] += (v[r] + vn) * c + tt * Qy;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int f = f0 + r, m = Nq + f;
+      const real *rm = rbase + m * kNodeRec;
+      const real wf = L.wf[f], nrf = L.nr[f], nsf = L.ns[f];
+      const real nJx = rx[r] * nrf + sx[r] * nsf, nJy = ry[r] * nrf + sy[r] * nsf;
+      const real h = rm[10], uu = real(2) * u[r], vv = real(2) * v[r], dH = rm[5];
+      const real huu = real(2) * hu[r], hvv = real(2) * hv[r];
+      const real *P = L.nb + (e * Nfq + f) * 4;
+      const real hP = P[0], uP = P[1], vP = P[2], dHP = P[3];
+      const real huP = hP * uP, hvP = hP * vP;
+      const real hua = real(0.5) * (huu + huP), hva = real(0.5) * (hvv + hvP);
+      const real ua = real(0.5) * (uu + uP), va = real(0.5) * (vv + vP);
+      const real pr = gh[r] * dHP;
+      real f0v = nJx * hua + nJy * hva;
+      real f1v = nJx * (hua * ua + pr) + nJy * hva * ua;
+      real f2v = nJx * hua * va + nJy * (hva * va + pr);
+      if (d.flux == 1) {
+        const real sJ = sqrt(nJx * nJx + nJy * nJy);
+        const real lm = fabs(uu * nJx + vv * nJy) + sqrt(g * h) * sJ;
+        const real lp = fabs(uP * nJx + vP * nJy) + sqrt(g * hP) * sJ;
+        const real c = real(0.5) * fmax(lm, lp);
+        f0v -= c * (dHP - dH);
+        f1v -= c * (huP - huu);
+        f2v -= c * (hvP - hvv);
+      }
+      L.R[0 * ne * Nh + e * Nh + m] = a0[r] + wf * f0v;
+      L.R[1 * ne * Nh + e * Nh + m] = a1[r] + wf * f1v;
+      L.R[2 * ne * Nh + e * Nh + m] = a2[r] + wf * f2v;
+    }
+  }
+}
 
+template <typename real, int N, int R>
+__device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm) {
+  constexpr int Np = dim_Np(N), Nh = dim_Nh(N);
+  const int tid = threadIdx.x, nth = blockDim.x;
+  Lds<real, N> L(sm, ne);
+  const real g = real(d.g);
+  fetch_tile<real, N>(a, d, k0, ne, L);
+  if (a.mode == kProject) {
+    const real *src = static_cast<const real *>(a.ext_state ? a.ext_state : d.uh);
+    const size_t splane = size_t(d.K) * Np;
+    for (int i = tid; i < 3 * ne * Np; i += nth) {
+      const int c = i / (ne * Np), r = i - c * ne * Np;
+      L.U[i] = src[c * splane + size_t(k0) * Np + r];
+    }
+    __syncthreads();
+    project_tile<real, N>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]), a.flag);
+    return;
+  }
+  __syncthreads();
+  // phase 1: node records from the fetched u~ and metric factors
   for (int i = tid; i < ne * Nh; i += nth) {
-    const int e = i / Nh, n = i - e * Nh;
-    const size_t o = size_t(k0 + e) * Nh + n;
-    const real h = ut[o], u = ut[plane + o], v = ut[2 * plane + o], dH = ut[3 * plane + o];
-    real *rec = sNode + i * kNodeRec;
+    const real h = L.raw[i], u = L.raw[ne * Nh + i], v = L.raw[2 * ne * Nh + i], dH = L.raw[3 * ne * Nh + i];
+    real *rec = L.rec + i * kNodeRec;
     rec[0] = real(0.5) * h * u;
     rec[1] = real(0.5) * h * v;
     rec[2] = real(0.5) * u;
     rec[3] = real(0.5) * v;
     rec[4] = real(0.5) * g * h;
     rec[5] = dH;
-    rec[6] = geo[o];
-    rec[7] = geo[plane + o];
-    rec[8] = geo[2 * plane + o];
-    rec[9] = geo[3 * plane + o];
+    rec[6] = L.raw[4 * ne * Nh + i];
+    rec[7] = L.raw[5 * ne * Nh + i];
+    rec[8] = L.raw[6 * ne * Nh + i];
+    rec[9] = L.raw[7 * ne * Nh + i];
     rec[10] = h;
   }
   __syncthreads();
-
-  // volume rows: every column n != m (volume-volume and volume-surface blocks)
-  for (int i = tid; i < ne * Nq; i += nth) {
-    const int e = i / Nq, m = i - e * Nq;
-    const real *rm = sNode + (e * Nh + m) * kNodeRec;
-    const real hum = rm[0], hvm = rm[1], um = rm[2], vm = rm[3], ghm = rm[4];
-    const real rxm = rm[6], sxm = rm[7], rym = rm[8], sym = rm[9];
-    real acc0 = 0, acc1 = 0, acc2 = 0;
-#pragma unroll 2
-    for (int n = 0; n < Nh; ++n) {
-      if (n == m) continue;
-      const real *rn = sNode + (e * Nh + n) * kNodeRec;
-      const real Sr = sSr[m * Nh + n], Ss = sSs[m * Nh + n];
-      const real Qx = (rxm + rn[6]) * Sr + (sxm + rn[7]) * Ss;
-      const real Qy = (rym + rn[8]) * Sr + (sym + rn[9]) * Ss;
-      const real c = Qx * (hum + rn[0]) + Qy * (hvm + rn[1]);
-      const real t = ghm * rn[5];
-      acc0 += c;
-      acc1 += (um + rn[2]) * c + t * Qx;
-      acc2 += (vm + rn[3]) * c + t * Qy;
-    }
-    sR[0 * ne * Nh + e * Nh + m] = acc0;
-    sR[1 * ne * Nh + e * Nh + m] = acc1;
-    sR[2 * ne * Nh + e * Nh + m] = acc2;
-  }
-
-  // face rows: volume columns (the surface-surface block is zero) + interface flux
-  const int32_t *mapP = d.mapP;
-  for (int i = tid; i < ne * Nfq; i += nth) {
-    const int e = i / Nfq, f = i - e * Nfq, m = Nq + f, k = k0 + e;
-    const real *rm = sNode + (e * Nh + m) * kNodeRec;
-    const real hum = rm[0], hvm = rm[1], um = rm[2], vm = rm[3], ghm = rm[4];
-    const real rxm = rm[6], sxm = rm[7], rym = rm[8], sym = rm[9];
-    real acc0 = 0, acc1 = 0, acc2 = 0;
-#pragma unroll 2
-    for (int n = 0; n < Nq; ++n) {
-      const real *rn = sNode + (e * Nh + n) * kNodeRec;
-      const real Sr = -sSr[n * Nh + m], Ss = -sSs[n * Nh + m];
-      const real Qx = (rxm + rn[6]) * Sr + (sxm + rn[7]) * Ss;
-      const real Qy = (rym + rn[8]) * Sr + (sym + rn[9]) * Ss;
-      const real c = Qx * (hum + rn[0]) + Qy * (hvm + rn[1]);
-      const real t = ghm * rn[5];
-      acc0 += c;
-      acc1 += (um + rn[2]) * c + t * Qx;
-      acc2 += (vm + rn[3]) * c + t * Qy;
-    }
-    // interface: W_f [ nJ . f_S(u~, u~+) + 1/2 g h (H+ - Href) nJ ] - LF
-    const real wf = sF[f], nr = sF[Nfq + f], ns = sF[2 * Nfq + f];
-    const real nJx = rxm * nr + sxm * ns, nJy = rym * nr + sym * ns;
-    const real h = rm[10], u = real(2) * um, v = real(2) * vm, dH = rm[5];
-    const real hu = real(2) * hum, hv = real(2) * hvm;
-    const int32_t p = mapP[size_t(k) * Nfq + f];
-    const real hP = ut[p], uP = ut[plane + p], vP = ut[2 * plane + p], dHP = ut[3 * plane + p];
-    const real huP = hP * uP, hvP = hP * vP;
-    const real hua = real(0.5) * (hu + huP), hva = real(0.5) * (hv + hvP);
-    const real ua = real(0.5) * (u + uP), va = real(0.5) * (v + vP);
-    const real pr = ghm * dHP;
-    real f0 = nJx * hua + nJy * hva;
-    real f1 = nJx * (hua * ua + pr) + nJy * hva * ua;
-    real f2 = nJx * hua * va + nJy * (hva * va + pr);
-    if (d.flux == 1) {
-      const real sJ = sqrt(nJx * nJx + nJy * nJy);
-      const real lm = fabs(u * nJx + v * nJy) + sqrt(g * h) * sJ;
-      const real lp = fabs(uP * nJx + vP * nJy) + sqrt(g * hP) * sJ;
-      const real c = real(0.5) * fmax(lm, lp);
-      f0 -= c * (dHP - dH);
-      f1 -= c * (huP - hu);
-      f2 -= c * (hvP - hv);
-    }
-    sR[0 * ne * Nh + e * Nh + m] = acc0 + wf * f0;
-    sR[1 * ne * Nh + e * Nh + m] = acc1 + wf * f1;
-    sR[2 * ne * Nh + e * Nh + m] = acc2 + wf * f2;
-  }
+  residual_tile<real, N, R>(d, ne, L);
   __syncthreads();
-
   // lift: y = V_h^T r_h
   for (int i = tid; i < ne * Np; i += nth) {
     const int e = i / Np, j = i - e * Np;
     real y0 = 0, y1 = 0, y2 = 0;
 #pragma unroll 4
     for (int n = 0; n < Nh; ++n) {
-      const real v = sVh[n * Np + j];
-      y0 += v * sR[0 * ne * Nh + e * Nh + n];
-      y1 += v * sR[1 * ne * Nh + e * Nh + n];
-      y2 += v * sR[2 * ne * Nh + e * Nh + n];
+      const real v = L.Vh[n * Np + j];
+      y0 += v * L.R[0 * ne * Nh + e * Nh + n];
+      y1 += v * L.R[1 * ne * Nh + e * Nh + n];
+      y2 += v * L.R[2 * ne * Nh + e * Nh + n];
     }
-    sB[0 * ne * Np + i] = y0;
-    sB[1 * ne * Np + i] = y1;
-    sB[2 * ne * Np + i] = y2;
+    L.T[0 * ne * Np + i] = y0;
+    L.T[1 * ne * Np + i] = y1;
+    L.T[2 * ne * Np + i] = y2;
   }
   __syncthreads();
-
-  // rhs = -Minv y; then either store it or do the LSRK update
-  const real *Minv = static_cast<const real *>(d.Minv);
-  const size_t splane = size_t(K) * Np;
+  // rhs = -Minv y; store it, or do the LSRK update
+  const size_t splane = size_t(d.K) * Np;
   real *uh = static_cast<real *>(d.uh);
   real *du = static_cast<real *>(d.du);
   real *rhs_out = static_cast<real *>(a.ext_rhs);
   const real ra = real(a.rk_a), rdt = real(d.dt), rb = real(a.rk_b);
   for (int i = tid; i < ne * Np; i += nth) {
-    const int e = i / Np, row = i - e * Np, k = k0 + e;
-    const real *Mi = Minv + (size_t(k) * Np + row) * Np;
+    const int e = i / Np, row = i - e * Np;
+    const real *Mi = L.Minv + (e * Np + row) * Np;
     real r0 = 0, r1 = 0, r2 = 0;
 #pragma unroll 4
     for (int j = 0; j < Np; ++j) {
       const real mm = Mi[j];
-      r0 -= mm * sB[0 * ne * Np + e * Np + j];
-      r1 -= mm * sB[1 * ne * Np + e * Np + j];
-      r2 -= mm * sB[2 * ne * Np + e * Np + j];
+      r0 -= mm * L.T[0 * ne * Np + e * Np + j];
+      r1 -= mm * L.T[1 * ne * Np + e * Np + j];
+      r2 -= mm * L.T[2 * ne * Np + e * Np + j];
     }
-    const size_t o = size_t(k) * Np + row;
+    const size_t o = size_t(k0) * Np + i;
     if (a.mode == kRhs) {
       rhs_out[o] = r0;
       rhs_out[splane + o] = r1;
@@ -275,61 +394,41 @@ __device__ void volume_tile(const StageArgs &a, const InstDesc &d, int k0, int n
       const real rr[3] = {r0, r1, r2};
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const size_t oc = c * splane + o;
-        const real dn = ra * du[oc] + rdt * rr[c];
-        const real un = uh[oc] + rb * dn;
-        du[oc] = dn;
-        uh[oc] = un;
-        sA[c * ne * Np + i] = un;
+        const real dn = ra * L.DU[c * ne * Np + i] + rdt * rr[c];
+        const real un = L.U[c * ne * Np + i] + rb * dn;
+        du[c * splane + o] = dn;
+        uh[c * splane + o] = un;
+        L.U[c * ne * Np + i] = un;
       }
     }
   }
   if (a.mode == kStage) {
     __syncthreads();
-    project_tile<real, N>(d, k0, ne, sVh, sA, sB, sNode, static_cast<real *>(d.ut[a.out_buf]), a.flag);
+    project_tile<real, N>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]), a.flag);
   }
 }
 
-template <typename real, int N>
-__device__ void process_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm) {
-  constexpr int words = ref_words(N);
-  const real *ref = static_cast<const real *>(d.ref);
-  for (int i = threadIdx.x; i < words; i += blockDim.x) sm[i] = ref[i];
-  if (a.mode == kProject) {
-    constexpr int Np = dim_Np(N), Nh = dim_Nh(N);
-    real *sNode = sm + words;
-    real *sA = sNode + ne * Nh * kNodeRec + 3 * ne * Nh;
-    real *sB = sA + 3 * ne * Np;
-    const real *src = static_cast<const real *>(a.ext_state ? a.ext_state : d.uh);
-    const size_t splane = size_t(d.K) * Np;
-    for (int i = threadIdx.x; i < 3 * ne * Np; i += blockDim.x) {
-      const int c = i / (ne * Np), r = i - c * ne * Np;
-      sA[i] = src[c * splane + size_t(k0) * Np + r];
-    }
-    __syncthreads();
-    project_tile<real, N>(d, k0, ne, sm, sA, sB, sNode, static_cast<real *>(d.ut[a.out_buf]), a.flag);
-  } else {
-    __syncthreads();
-    volume_tile<real, N>(a, d, k0, ne, sm);
-  }
-}
+// Rows per thread in the residual phase, per degree (must divide Nq and Nfq).
+template <int N> struct RowsPerThread { static constexpr int value = 1; };
 
 template <typename real>
-__global__ void __launch_bounds__(kBlock, 4) stage_kernel(StageArgs a) {
+__global__ void __launch_bounds__(kBlock, 2) stage_kernel(StageArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   real *sm = reinterpret_cast<real *>(smem_raw);
-  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-    const Tile tl = a.tiles[t];
-    const InstDesc &d = a.desc[tl.inst];
-    switch (d.N) {
-      case 1: process_tile<real, 1>(a, d, tl.k0, tl.ne, sm); break;
-      case 2: process_tile<real, 2>(a, d, tl.k0, tl.ne, sm); break;
-      case 3: process_tile<real, 3>(a, d, tl.k0, tl.ne, sm); break;
-      case 4: process_tile<real, 4>(a, d, tl.k0, tl.ne, sm); break;
-      case 5: process_tile<real, 5>(a, d, tl.k0, tl.ne, sm); break;
-      default: break;
-    }
-    __syncthreads();
+  // blocks are dealt to the XCDs round-robin; give each XCD a contiguous range of
+  // tiles so face neighbours written by the previous stage tend to share an L2
+  const int per = int(gridDim.x) / kXcds;
+  const int t = (int(blockIdx.x) % kXcds) * per + int(blockIdx.x) / kXcds;
+  if (t >= a.ntiles) return;
+  const Tile tl = a.tiles[t];
+  const InstDesc &d = a.desc[tl.inst];
+  switch (d.N) {
+    case 1: stage_tile<real, 1, RowsPerThread<1>::value>(a, d, tl.k0, tl.ne, sm); break;
+    case 2: stage_tile<real, 2, RowsPerThread<2>::value>(a, d, tl.k0, tl.ne, sm); break;
+    case 3: stage_tile<real, 3, RowsPerThread<3>::value>(a, d, tl.k0, tl.ne, sm); break;
+    case 4: stage_tile<real, 4, RowsPerThread<4>::value>(a, d, tl.k0, tl.ne, sm); break;
+    case 5: stage_tile<real, 5, RowsPerThread<5>::value>(a, d, tl.k0, tl.ne, sm); break;
+    default: break;
   }
 }
 
@@ -337,10 +436,11 @@ __global__ void __launch_bounds__(kBlock, 4) stage_kernel(StageArgs a) {
 template <typename real, int N>
 __device__ void diag_tile(const InstDesc &d, int k0, int ne, double *acc) {
   constexpr int Np = dim_Np(N), Nq = dim_Nq(N);
-  const real *ref = static_cast<const real *>(d.ref);   // Vh rows 0..Nq-1 are V_q
+  const real *ref = static_cast<const real *>(d.ref);   // V_h rows 0..Nq-1 are V_q
   const real *uh = static_cast<const real *>(d.uh);
   const real *rh = static_cast<const real *>(d.rhs_scratch);
   const real *wJq = static_cast<const real *>(d.wJq);
+  const real *bq = static_cast<const real *>(d.bq);
   const size_t splane = size_t(d.K) * Np;
   const double g = d.g;
   for (int i = threadIdx.x; i < ne * Nq; i += blockDim.x) {
@@ -353,9 +453,9 @@ __device__ void diag_tile(const InstDesc &d, int k0, int ne, double *acc) {
         r[c] += v * double(rh[c * splane + size_t(k) * Np + j]);
       }
     }
-    const double w = wJq[size_t(k) * Nq + q], b = d.bq[size_t(k) * Nq + q];
-    const double h = u[0], uu = u[1] / h, vv = u[2] / h;
-    acc[0] += w * u[0];
+    const double w = wJq[size_t(k) * Nq + q], b = bq[size_t(k) * Nq + q];
+    const double h = u[0] + d.Href - b, uu = u[1] / h, vv = u[2] / h;
+    acc[0] += w * h;
     acc[1] += w * u[1];
     acc[2] += w * u[2];
     acc[3] += w * (0.5 * h * (uu * uu + vv * vv) + 0.5 * g * h * h + g * h * b);
@@ -401,8 +501,13 @@ hipError_t set_stage_lds_limit(bool fp64, size_t lds_bytes) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
 }
 
-hipError_t launch_stage(bool fp64, const StageArgs &a, int grid, size_t lds_bytes, hipStream_t stream) {
-  if (grid <= 0) return hipSuccess;
+// Grid of a stage launch over ntiles tiles: whole rounds of kXcds blocks, so the
+// block -> tile map in stage_kernel is a bijection onto [0, grid).
+int stage_grid(int ntiles) { return ((ntiles + kXcds - 1) / kXcds) * kXcds; }
+
+hipError_t launch_stage(bool fp64, const StageArgs &a, int ntiles, size_t lds_bytes, hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  const int grid = stage_grid(ntiles);
   if (fp64)
     hipLaunchKernelGGL(stage_kernel<double>, dim3(grid), dim3(kBlock), lds_bytes, stream, a);
   else

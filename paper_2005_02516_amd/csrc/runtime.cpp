@@ -111,8 +111,16 @@ std::vector<double> ref_block(const RefElem &R) {
   std::vector<double> b;
   b.reserve(ref_words(R.N));
   b.insert(b.end(), R.Vh.a.begin(), R.Vh.a.end());
-  b.insert(b.end(), R.Sr.a.begin(), R.Sr.a.end());
-  b.insert(b.end(), R.Ss.a.begin(), R.Ss.a.end());
+  for (int n = 0; n < R.Nh; ++n)
+    for (int m = 0; m < R.Nq; ++m) {
+      b.push_back(R.Sr(m, n));
+      b.push_back(R.Ss(m, n));
+    }
+  for (int n = 0; n < R.Nq; ++n)
+    for (int f = 0; f < R.Nfq; ++f) {
+      b.push_back(-R.Sr(n, R.Nq + f));
+      b.push_back(-R.Ss(n, R.Nq + f));
+    }
   b.insert(b.end(), R.wf.begin(), R.wf.end());
   b.insert(b.end(), R.nr.begin(), R.nr.end());
   b.insert(b.end(), R.ns.begin(), R.ns.end());
@@ -173,8 +181,16 @@ esdg_status set_modal(esdg_swe *s, int inst, const std::vector<double> &uh) {
       sum += w * (hq + H.bq[size_t(k) * R.Nq + q]);
       wsum += w;
     }
-  s->desc[inst].Href = sum / wsum;
-  auto bulk = to_bulk(uh, s->fp64);
+  const double Href = sum / wsum;
+  s->desc[inst].Href = Href;
+  // internal depth: eta = h + b - Href (modal; the constant 1 is sqrt(2) phi_0)
+  std::vector<double> w = uh;
+  const double c0 = std::sqrt(2.0);
+  for (int k = 0; k < H.K; ++k) {
+    for (int j = 0; j < R.Np; ++j) w[size_t(k) * R.Np + j] += H.bmodal[size_t(k) * R.Np + j];
+    w[size_t(k) * R.Np] -= Href * c0;
+  }
+  auto bulk = to_bulk(w, s->fp64);
   esdg_status st = upload(s, s->off[inst].uh, bulk.data(), bulk.size());
   if (st) return st;
   hipError_t e = hipMemsetAsync(s->ws + s->off[inst].du, 0, n * s->word, s->stream);
@@ -282,8 +298,8 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
     f.geo = take(4 * K * Nh * w);
     f.wJq = take(K * Nq * w);
     f.Minv = take(K * Np * Np * w);
-    f.bq = take(K * Nq * 8);
-    f.bh = take(K * Nh * 8);
+    f.bq = take(K * Nq * w);
+    f.bh = take(K * Nh * w);
     f.mapP = take(K * Nfq * 4);
     f.rhs = take(3 * K * Np * w);
   }
@@ -325,8 +341,10 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
     if ((st = upload(s, f.wJq, keep.back().data(), keep.back().size()))) return st;
     keep.push_back(to_bulk(H.Minv, s->fp64));
     if ((st = upload(s, f.Minv, keep.back().data(), keep.back().size()))) return st;
-    if ((st = upload(s, f.bq, H.bq.data(), H.bq.size() * 8))) return st;
-    if ((st = upload(s, f.bh, H.bh.data(), H.bh.size() * 8))) return st;
+    keep.push_back(to_bulk(H.bq, s->fp64));
+    if ((st = upload(s, f.bq, keep.back().data(), keep.back().size()))) return st;
+    keep.push_back(to_bulk(H.bh, s->fp64));
+    if ((st = upload(s, f.bh, keep.back().data(), keep.back().size()))) return st;
     if ((st = upload(s, f.mapP, H.mapP.data(), H.mapP.size() * 4))) return st;
     InstDesc &d = s->desc[i];
     d.N = H.N;
@@ -341,8 +359,8 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
     d.geo = s->ws + f.geo;
     d.wJq = s->ws + f.wJq;
     d.Minv = s->ws + f.Minv;
-    d.bq = s->dev<double>(f.bq);
-    d.bh = s->dev<double>(f.bh);
+    d.bq = s->ws + f.bq;
+    d.bh = s->ws + f.bh;
     d.mapP = s->dev<int32_t>(f.mapP);
     d.ref = s->ws + s->ref_off[H.N];
     d.rhs_scratch = s->ws + f.rhs;
@@ -391,6 +409,13 @@ esdg_status esdg_swe_get_state(esdg_swe *s, int32_t inst, double *uh) {
     std::memcpy(uh, buf.data(), buf.size());
   else
     for (size_t i = 0; i < n; ++i) uh[i] = reinterpret_cast<const float *>(buf.data())[i];
+  // eta -> h
+  const int Np = dim_Np(H.N);
+  const double Href = s->desc[inst].Href, c0 = std::sqrt(2.0);
+  for (int k = 0; k < H.K; ++k) {
+    for (int j = 0; j < Np; ++j) uh[size_t(k) * Np + j] -= H.bmodal[size_t(k) * Np + j];
+    uh[size_t(k) * Np] += Href * c0;
+  }
   return st;
 }
 
@@ -534,6 +559,13 @@ esdg_status esdg_swe_query(const esdg_swe *s, int32_t inst, int32_t *out6) {
   out6[3] = dim_Nq(N);
   out6[4] = dim_Nfq(N);
   out6[5] = dim_Nh(N);
+  return ESDG_OK;
+}
+
+esdg_status esdg_swe_reference_level(const esdg_swe *s, int32_t inst, double *Href) {
+  if (!s || !Href || inst < 0 || inst >= s->n_inst) return ESDG_EINVAL;
+  if (!s->state_set[inst]) return ESDG_ESTATE;
+  *Href = s->desc[inst].Href;
   return ESDG_OK;
 }
 
