@@ -48,11 +48,14 @@ _lib = None
 
 
 def load_library(path: Optional[str] = None) -> C.CDLL:
-    """Load libesdg_swe.so and declare its signatures (no GPU needed for loading)."""
+    """Load libesdg_swe.so and declare its signatures (no GPU needed for loading).
+
+    The in-tree build is used unless ``path`` or the ESDG_SWE_LIBRARY environment
+    variable names another build of the same library."""
     global _lib
     if _lib is not None and path is None:
         return _lib
-    p = path or library_path()
+    p = path or os.environ.get("ESDG_SWE_LIBRARY") or library_path()
     if not os.path.exists(p):
         raise ImportError(f"{p} is missing: build it with `python -m paper_2005_02516_amd.build`")
     lib = C.CDLL(p)

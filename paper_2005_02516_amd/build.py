@@ -11,6 +11,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIBDIR = os.path.join(HERE, "_lib")
 LIBNAME = "libesdg_swe.so"
 SOURCES = ["host_setup.cpp", "kernels.hip", "runtime.cpp"]
@@ -34,7 +35,7 @@ def build_library(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(LIBDIR, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [hipcc, *HIPFLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *HIPFLAGS, "-I" + INCLUDE, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

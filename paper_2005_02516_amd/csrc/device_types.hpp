@@ -27,12 +27,12 @@ __host__ __device__ constexpr int ref_words(int N) {
   return dim_Nh(N) * dim_Np(N) + 2 * dim_Nh(N) * dim_Nq(N) + 2 * dim_Nq(N) * dim_Nfq(N) + 3 * dim_Nfq(N);
 }
 
-// Words (of the bulk precision) of LDS a workgroup needs for E elements of degree N:
-// ref block | node records [E][Nh][kNodeRec] | fetched u~ and metrics [8][E][Nh] |
+// Words (of the bulk precision) of LDS one tile of E elements of degree N needs (the
+// reference block is held separately, once per workgroup): node records [E][Nh][kNodeRec] | fetched u~ and metrics [8][E][Nh] |
 // neighbour values [E][Nfq][4] | state, RK register [3][E][Np] each | Minv [E][Np][Np] |
 // w J [E][Nq] | b at volume nodes [E][Nq] | b at hybrid nodes [E][Nh].
-__host__ __device__ constexpr int lds_words(int N, int E) {
-  return ref_words(N) + E * (dim_Nh(N) * kNodeRec + 8 * dim_Nh(N) + 4 * dim_Nfq(N) + 6 * dim_Np(N) +
+__host__ __device__ constexpr int tile_words(int N, int E) {
+  return E * (dim_Nh(N) * kNodeRec + 8 * dim_Nh(N) + 4 * dim_Nfq(N) + 6 * dim_Np(N) +
                              dim_Np(N) * dim_Np(N) + 2 * dim_Nq(N) + dim_Nh(N));
 }
 
@@ -69,6 +69,8 @@ struct StageArgs {
   const Tile *tiles;
   int32_t ntiles;
   int32_t mode;
+  int32_t ref_words_max;  // LDS words reserved for the reference block (largest degree)
+  int32_t pad;
   int32_t in_buf, out_buf;
   double rk_a, rk_b;
   const void *ext_state;  // kProject: read this state instead of desc.uh (when non-null)

@@ -42,7 +42,8 @@ struct Lds {
   real *ref, *Vh, *ST, *FT, *wf, *nr, *ns;
   real *rec, *raw, *nb, *U, *DU, *Minv, *wJ, *bq, *bh;
   real *R, *T, *Q;
-  __device__ Lds(real *sm, int E) {
+  // sm: the ref block (already loaded); tile: the tile region (after the largest ref block)
+  __device__ Lds(real *sm, real *tile, int E) {
     ref = sm;
     Vh = ref;
     ST = Vh + Nh * Np;
@@ -50,7 +51,7 @@ struct Lds {
     wf = FT + 2 * Nq * Nfq;
     nr = wf + Nfq;
     ns = nr + Nfq;
-    rec = sm + ref_words(N);
+    rec = tile;
     raw = rec + E * Nh * kNodeRec;
     nb = raw + 8 * E * Nh;
     U = nb + 4 * E * Nfq;
@@ -101,35 +102,25 @@ __device__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L,
     bad |= bad_value(h, hu, hv);
   }
   __syncthreads();
-  for (int i = tid; i < ne * Np; i += nth) {
-    const int e = i / Np, j = i - e * Np;
-    real y0 = 0, y1 = 0, y2 = 0;
+  // y = V_q^T (w J v'): one task per (field, element, mode)
+  for (int i = tid; i < 3 * ne * Np; i += nth) {
+    const int c = i / (ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
+    const real *Qc = L.Q + c * ne * Nq + e * Nq;
+    real y = 0;
 #pragma unroll 4
-    for (int q = 0; q < Nq; ++q) {
-      const real v = L.Vh[q * Np + j];
-      y0 += v * L.Q[0 * ne * Nq + e * Nq + q];
-      y1 += v * L.Q[1 * ne * Nq + e * Nq + q];
-      y2 += v * L.Q[2 * ne * Nq + e * Nq + q];
-    }
-    L.T[0 * ne * Np + i] = y0;
-    L.T[1 * ne * Np + i] = y1;
-    L.T[2 * ne * Np + i] = y2;
+    for (int q = 0; q < Nq; ++q) y += L.Vh[q * Np + j] * Qc[q];
+    L.T[i] = y;
   }
   __syncthreads();
-  for (int i = tid; i < ne * Np; i += nth) {
-    const int e = i / Np, row = i - e * Np;
+  // v'_h = Minv_k y
+  for (int i = tid; i < 3 * ne * Np; i += nth) {
+    const int c = i / (ne * Np), r = i - c * ne * Np, e = r / Np, row = r - e * Np;
     const real *Mi = L.Minv + (e * Np + row) * Np;
-    real v0 = 0, v1 = 0, v2 = 0;
+    const real *Tc = L.T + c * ne * Np + e * Np;
+    real v = 0;
 #pragma unroll 4
-    for (int j = 0; j < Np; ++j) {
-      const real m = Mi[j];
-      v0 += m * L.T[0 * ne * Np + e * Np + j];
-      v1 += m * L.T[1 * ne * Np + e * Np + j];
-      v2 += m * L.T[2 * ne * Np + e * Np + j];
-    }
-    L.U[0 * ne * Np + i] = v0;
-    L.U[1 * ne * Np + i] = v1;
-    L.U[2 * ne * Np + i] = v2;
+    for (int j = 0; j < Np; ++j) v += Mi[j] * Tc[j];
+    L.U[i] = v;
   }
   __syncthreads();
   const size_t plane = size_t(K) * Nh;
@@ -162,8 +153,6 @@ __device__ void fetch_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
   constexpr int Np = dim_Np(N), Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
   const int tid = threadIdx.x, nth = blockDim.x;
   const size_t plane = size_t(d.K) * Nh, splane = size_t(d.K) * Np;
-  const real *ref = static_cast<const real *>(d.ref);
-  for (int i = tid; i < ref_words(N); i += nth) L.ref[i] = ref[i];
   if (a.mode != kProject) {
     const real *ut = static_cast<const real *>(d.ut[a.in_buf]);
     const real *geo = static_cast<const real *>(d.geo);
@@ -206,84 +195,50 @@ __device__ void fetch_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
 }
 
 // Phase 2+3: residual rows, R rows of one element per thread.
-template <typename real, int N, int R>
-__device__ void residual_tile(const InstDesc &d, int ne, Lds<real, N> &L) {
+template <typename real, int N, int R, bool FACE>
+__device__ inline void row_block(const InstDesc &d, int ne, int e, int b, Lds<real, N> &L) {
   constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
-  constexpr int VB = Nq / R, FB = Nfq / R;
-  static_assert(Nq % R == 0 && Nfq % R == 0, "R must divide Nq and Nfq");
-  const int tid = threadIdx.x, nth = blockDim.x;
+  // volume rows: all Nh columns (the diagonal of the skew operator is zero);
+  // face rows: the Nq volume columns (the surface-surface block is zero)
+  constexpr int NCOL = FACE ? Nq : Nh;
+  constexpr int LD = FACE ? Nfq : Nq;
+  const int r0 = b * R;                       // first row within the row set
+  const int m0 = FACE ? Nq + r0 : r0;         // first hybrid-node index
+  const real *Stab = FACE ? L.FT : L.ST;
   const real g = real(d.g);
-  // volume rows: all Nh columns (the diagonal of the skew operator is zero)
-  for (int t = tid; t < ne * VB; t += nth) {
-    const int e = t / VB, m0 = (t - e * VB) * R;
-    const real *rbase = L.rec + e * Nh * kNodeRec;
-    real hu[R], hv[R], u[R], v[R], gh[R], rx[R], sx[R], ry[R], sy[R], a0[R], a1[R], a2[R];
+  const real *rbase = L.rec + e * Nh * kNodeRec;
+  real hu[R], hv[R], u[R], v[R], gh[R], rx[R], sx[R], ry[R], sy[R], a0[R], a1[R], a2[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const real *rm = rbase + (m0 + r) * kNodeRec;
-      hu[r] = rm[0]; hv[r] = rm[1]; u[r] = rm[2]; v[r] = rm[3]; gh[r] = rm[4];
-      rx[r] = rm[6]; sx[r] = rm[7]; ry[r] = rm[8]; sy[r] = rm[9];
-      a0[r] = 0; a1[r] = 0; a2[r] = 0;
-    }
+  for (int r = 0; r < R; ++r) {
+    const real *rm = rbase + (m0 + r) * kNodeRec;
+    hu[r] = rm[0]; hv[r] = rm[1]; u[r] = rm[2]; v[r] = rm[3]; gh[r] = rm[4];
+    rx[r] = rm[6]; sx[r] = rm[7]; ry[r] = rm[8]; sy[r] = rm[9];
+    a0[r] = 0; a1[r] = 0; a2[r] = 0;
+  }
 #pragma unroll 2
-    for (int n = 0; n < Nh; ++n) {
-      const real *rn = rbase + n * kNodeRec;
-      const real hun = rn[0], hvn = rn[1], un = rn[2], vn = rn[3], dHn = rn[5];
-      const real rxn = rn[6], sxn = rn[7], ryn = rn[8], syn = rn[9];
-      const real *S = L.ST + (n * Nq + m0) * 2;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const real Sr = S[2 * r], Ss = S[2 * r + 1];
-        const real Qx = (rx[r] + rxn) * Sr + (sx[r] + sxn) * Ss;
-        const real Qy = (ry[r] + ryn) * Sr + (sy[r] + syn) * Ss;
-        const real c = Qx * (hu[r] + hun) + Qy * (hv[r] + hvn);
-        const real t = gh[r] * dHn;
-        a0[r] += c;
-        a1[r] += (u[r] + un) * c + t * Qx;
-        a2[r] += (v[r] + vn) * c + t * Qy;
-      }
-    }
+  for (int n = 0; n < NCOL; ++n) {
+    const real *rn = rbase + n * kNodeRec;
+    const real hun = rn[0], hvn = rn[1], un = rn[2], vn = rn[3], dHn = rn[5];
+    const real rxn = rn[6], sxn = rn[7], ryn = rn[8], syn = rn[9];
+    const real *S = Stab + (n * LD + r0) * 2;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      L.R[0 * ne * Nh + e * Nh + m0 + r] = a0[r];
-      L.R[1 * ne * Nh + e * Nh + m0 + r] = a1[r];
-      L.R[2 * ne * Nh + e * Nh + m0 + r] = a2[r];
+      const real Sr = S[2 * r], Ss = S[2 * r + 1];
+      const real Qx = (rx[r] + rxn) * Sr + (sx[r] + sxn) * Ss;
+      const real Qy = (ry[r] + ryn) * Sr + (sy[r] + syn) * Ss;
+      const real c = Qx * (hu[r] + hun) + Qy * (hv[r] + hvn);
+      const real t = gh[r] * dHn;
+      a0[r] += c;
+      a1[r] += (u[r] + un) * c + t * Qx;
+      a2[r] += (v[r] + vn) * c + t * Qy;
     }
   }
-  // face rows: volume columns only (the surface-surface block is zero), then the
-  // interface flux W_f [ nJ . f_S(u~, u~+) + 1/2 g h (H+ - Href) nJ ] - LF
-  for (int t = tid; t < ne * FB; t += nth) {
-    const int e = t / FB, f0 = (t - e * FB) * R;
-    const real *rbase = L.rec + e * Nh * kNodeRec;
-    real hu[R], hv[R], u[R], v[R], gh[R], rx[R], sx[R], ry[R], sy[R], a0[R], a1[R], a2[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const real *rm = rbase + (Nq + f0 + r) * kNodeRec;
-      hu[r] = rm[0]; hv[r] = rm[1]; u[r] = rm[2]; v[r] = rm[3]; gh[r] = rm[4];
-      rx[r] = rm[6]; sx[r] = rm[7]; ry[r] = rm[8]; sy[r] = rm[9];
-      a0[r] = 0; a1[r] = 0; a2[r] = 0;
-    }
-#pragma unroll 2
-    for (int n = 0; n < Nq; ++n) {
-      const real *rn = rbase + n * kNodeRec;
-      const real hun = rn[0], hvn = rn[1], un = rn[2], vn = rn[3], dHn = rn[5];
-      const real rxn = rn[6], sxn = rn[7], ryn = rn[8], syn = rn[9];
-      const real *S = L.FT + (n * Nfq + f0) * 2;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const real Sr = S[2 * r], Ss = S[2 * r + 1];
-        const real Qx = (rx[r] + rxn) * Sr + (sx[r] + sxn) * Ss;
-        const real Qy = (ry[r] + ryn) * Sr + (sy[r] + syn) * Ss;
-        const real c = Qx * (hu[r] + hun) + Qy * (hv[r] + hvn);
-        const real tt = gh[r] * dHn;
-        a0[r] += c;
-        a1[r] += (u[r] + un) * c + tt * Qx;
-        a2[r] += (v[r] + vn) * c + tt * Qy;
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int f = f0 + r, m = Nq + f;
+  for (int r = 0; r < R; ++r) {
+    const int m = m0 + r;
+    if (FACE) {
+      // interface flux W_f [ nJ . f_S(u~, u~+) + 1/2 g h (H+ - Href) nJ ] - LF penalty
+      const int f = r0 + r;
       const real *rm = rbase + m * kNodeRec;
       const real wf = L.wf[f], nrf = L.nr[f], nsf = L.ns[f];
       const real nJx = rx[r] * nrf + sx[r] * nsf, nJy = ry[r] * nrf + sy[r] * nsf;
@@ -307,18 +262,41 @@ __device__ void residual_tile(const InstDesc &d, int ne, Lds<real, N> &L) {
         f1v -= c * (huP - huu);
         f2v -= c * (hvP - hvv);
       }
-      L.R[0 * ne * Nh + e * Nh + m] = a0[r] + wf * f0v;
-      L.R[1 * ne * Nh + e * Nh + m] = a1[r] + wf * f1v;
-      L.R[2 * ne * Nh + e * Nh + m] = a2[r] + wf * f2v;
+      a0[r] += wf * f0v;
+      a1[r] += wf * f1v;
+      a2[r] += wf * f2v;
+    }
+    L.R[0 * ne * Nh + e * Nh + m] = a0[r];
+    L.R[1 * ne * Nh + e * Nh + m] = a1[r];
+    L.R[2 * ne * Nh + e * Nh + m] = a2[r];
+  }
+}
+
+// Phase 2+3: residual rows.  One flat task list: first every volume row block of every
+// element, then every face row block, so whole waves take the same branch.
+template <typename real, int N, int R>
+__device__ void residual_tile(const InstDesc &d, int ne, Lds<real, N> &L) {
+  constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N);
+  constexpr int VB = Nq / R, FB = Nfq / R;
+  static_assert(Nq % R == 0 && Nfq % R == 0, "R must divide Nq and Nfq");
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int nv = ne * VB, ntask = nv + ne * FB;
+  for (int t = tid; t < ntask; t += nth) {
+    if (t < nv) {
+      const int e = t / VB;
+      row_block<real, N, R, false>(d, ne, e, t - e * VB, L);
+    } else {
+      const int tf = t - nv, e = tf / FB;
+      row_block<real, N, R, true>(d, ne, e, tf - e * FB, L);
     }
   }
 }
 
 template <typename real, int N, int R>
-__device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm) {
+__device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm, real *tile) {
   constexpr int Np = dim_Np(N), Nh = dim_Nh(N);
   const int tid = threadIdx.x, nth = blockDim.x;
-  Lds<real, N> L(sm, ne);
+  Lds<real, N> L(sm, tile, ne);
   const real g = real(d.g);
   fetch_tile<real, N>(a, d, k0, ne, L);
   if (a.mode == kProject) {
@@ -352,20 +330,14 @@ __device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
   __syncthreads();
   residual_tile<real, N, R>(d, ne, L);
   __syncthreads();
-  // lift: y = V_h^T r_h
-  for (int i = tid; i < ne * Np; i += nth) {
-    const int e = i / Np, j = i - e * Np;
-    real y0 = 0, y1 = 0, y2 = 0;
+  // lift: y = V_h^T r_h, one task per (field, element, mode)
+  for (int i = tid; i < 3 * ne * Np; i += nth) {
+    const int c = i / (ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
+    const real *Rc = L.R + c * ne * Nh + e * Nh;
+    real y = 0;
 #pragma unroll 4
-    for (int n = 0; n < Nh; ++n) {
-      const real v = L.Vh[n * Np + j];
-      y0 += v * L.R[0 * ne * Nh + e * Nh + n];
-      y1 += v * L.R[1 * ne * Nh + e * Nh + n];
-      y2 += v * L.R[2 * ne * Nh + e * Nh + n];
-    }
-    L.T[0 * ne * Np + i] = y0;
-    L.T[1 * ne * Np + i] = y1;
-    L.T[2 * ne * Np + i] = y2;
+    for (int n = 0; n < Nh; ++n) y += L.Vh[n * Np + j] * Rc[n];
+    L.T[i] = y;
   }
   __syncthreads();
   // rhs = -Minv y; store it, or do the LSRK update
@@ -411,24 +383,40 @@ __device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
 // Rows per thread in the residual phase, per degree (must divide Nq and Nfq).
 template <int N> struct RowsPerThread { static constexpr int value = 1; };
 
+// Persistent stage kernel: block b walks a contiguous range of tiles.  Blocks are dealt
+// to the XCDs round-robin, so block b's range is chosen as range number
+// (b mod kXcds) * (gridDim / kXcds) + b / kXcds: each XCD owns a contiguous run of tiles
+// and face neighbours written by the previous stage tend to sit in its L2.  The
+// reference-operator block stays in LDS and is reloaded only when the degree changes.
 template <typename real>
 __global__ void __launch_bounds__(kBlock, 2) stage_kernel(StageArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   real *sm = reinterpret_cast<real *>(smem_raw);
-  // blocks are dealt to the XCDs round-robin; give each XCD a contiguous range of
-  // tiles so face neighbours written by the previous stage tend to share an L2
-  const int per = int(gridDim.x) / kXcds;
-  const int t = (int(blockIdx.x) % kXcds) * per + int(blockIdx.x) / kXcds;
-  if (t >= a.ntiles) return;
-  const Tile tl = a.tiles[t];
-  const InstDesc &d = a.desc[tl.inst];
-  switch (d.N) {
-    case 1: stage_tile<real, 1, RowsPerThread<1>::value>(a, d, tl.k0, tl.ne, sm); break;
-    case 2: stage_tile<real, 2, RowsPerThread<2>::value>(a, d, tl.k0, tl.ne, sm); break;
-    case 3: stage_tile<real, 3, RowsPerThread<3>::value>(a, d, tl.k0, tl.ne, sm); break;
-    case 4: stage_tile<real, 4, RowsPerThread<4>::value>(a, d, tl.k0, tl.ne, sm); break;
-    case 5: stage_tile<real, 5, RowsPerThread<5>::value>(a, d, tl.k0, tl.ne, sm); break;
-    default: break;
+  real *tile = sm + a.ref_words_max;
+  const int G = int(gridDim.x);
+  const int chunk = (int(blockIdx.x) % kXcds) * (G / kXcds) + int(blockIdx.x) / kXcds;
+  const int t0 = int((long long)chunk * a.ntiles / G);
+  const int t1 = int((long long)(chunk + 1) * a.ntiles / G);
+  int loaded_N = 0;
+  for (int t = t0; t < t1; ++t) {
+    const Tile tl = a.tiles[t];
+    const InstDesc &d = a.desc[tl.inst];
+    if (d.N != loaded_N) {
+      __syncthreads();
+      const real *ref = static_cast<const real *>(d.ref);
+      const int words = ref_words(d.N);
+      for (int i = threadIdx.x; i < words; i += blockDim.x) sm[i] = ref[i];
+      loaded_N = d.N;
+    }
+    switch (d.N) {
+      case 1: stage_tile<real, 1, RowsPerThread<1>::value>(a, d, tl.k0, tl.ne, sm, tile); break;
+      case 2: stage_tile<real, 2, RowsPerThread<2>::value>(a, d, tl.k0, tl.ne, sm, tile); break;
+      case 3: stage_tile<real, 3, RowsPerThread<3>::value>(a, d, tl.k0, tl.ne, sm, tile); break;
+      case 4: stage_tile<real, 4, RowsPerThread<4>::value>(a, d, tl.k0, tl.ne, sm, tile); break;
+      case 5: stage_tile<real, 5, RowsPerThread<5>::value>(a, d, tl.k0, tl.ne, sm, tile); break;
+      default: break;
+    }
+    __syncthreads();
   }
 }
 
@@ -495,19 +483,37 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagArgs a) {
 
 // ---------------------------------------------------------------- host launchers
 
+// Workgroups of the stage kernel that stay resident on the whole device.
+hipError_t stage_max_blocks(bool fp64, size_t lds_bytes, int *out) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const void *fn = fp64 ? reinterpret_cast<const void *>(&stage_kernel<double>)
+                        : reinterpret_cast<const void *>(&stage_kernel<float>);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, lds_bytes);
+  if (e != hipSuccess) return e;
+  *out = ncu * (per_cu > 0 ? per_cu : 1);
+  return hipSuccess;
+}
+
 hipError_t set_stage_lds_limit(bool fp64, size_t lds_bytes) {
   const void *fn = fp64 ? reinterpret_cast<const void *>(&stage_kernel<double>)
                         : reinterpret_cast<const void *>(&stage_kernel<float>);
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
 }
 
-// Grid of a stage launch over ntiles tiles: whole rounds of kXcds blocks, so the
-// block -> tile map in stage_kernel is a bijection onto [0, grid).
-int stage_grid(int ntiles) { return ((ntiles + kXcds - 1) / kXcds) * kXcds; }
+// Persistent grid: at most max_blocks (what stays resident), at most one block per tile,
+// always a whole number of XCD rounds (blocks whose range is empty just exit).
+int stage_grid(int ntiles, int max_blocks) {
+  int g = ntiles < max_blocks ? ntiles : max_blocks;
+  return ((g + kXcds - 1) / kXcds) * kXcds;
+}
 
-hipError_t launch_stage(bool fp64, const StageArgs &a, int ntiles, size_t lds_bytes, hipStream_t stream) {
-  if (ntiles <= 0) return hipSuccess;
-  const int grid = stage_grid(ntiles);
+hipError_t launch_stage(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream) {
+  if (a.ntiles <= 0) return hipSuccess;
+  const int grid = stage_grid(a.ntiles, max_blocks);
   if (fp64)
     hipLaunchKernelGGL(stage_kernel<double>, dim3(grid), dim3(kBlock), lds_bytes, stream, a);
   else

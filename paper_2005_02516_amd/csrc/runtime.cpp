@@ -11,13 +11,14 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/esdg_swe.h"
+#include "esdg_swe.h"
 #include "device_types.hpp"
 #include "host_setup.hpp"
 
 namespace esdg {
 hipError_t set_stage_lds_limit(bool fp64, size_t lds_bytes);
-hipError_t launch_stage(bool fp64, const StageArgs &a, int grid, size_t lds_bytes, hipStream_t stream);
+hipError_t launch_stage(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream);
+hipError_t stage_max_blocks(bool fp64, size_t lds_bytes, int *out);
 hipError_t launch_diag(bool fp64, const DiagArgs &a, hipStream_t stream);
 }  // namespace esdg
 
@@ -36,12 +37,13 @@ thread_local std::string g_init_error;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Default elements per workgroup: as many as keep E*Nh <= 512 and LDS <= 48 KiB.
+// Default elements per workgroup: as many as keep E*Nh <= 512 and the tile's LDS
+// <= 40 KiB (with the reference block, several workgroups stay resident per CU).
 int default_epb(int N, size_t word) {
   int best = 1;
   for (int E = 1; E <= 64; E *= 2) {
     if (E * dim_Nh(N) > 512) break;
-    if (size_t(lds_words(N, E)) * word > 48 * 1024) break;
+    if (size_t(tile_words(N, E)) * word > 40 * 1024) break;
     best = E;
   }
   return best;
@@ -66,6 +68,8 @@ struct esdg_swe {
   size_t ws_bytes = 0;
   std::map<int, int> epb;          // elements per workgroup per N
   size_t lds_bytes = 0;
+  int ref_max = 0;                 // LDS words reserved for the largest reference block
+  int max_blocks = 0;              // resident workgroups of the stage kernel (set at bind)
   std::vector<Tile> tiles;
   std::vector<int> tile_begin, tile_count;
   std::vector<InstDesc> desc;
@@ -133,8 +137,8 @@ esdg_status upload(esdg_swe *s, size_t off, const void *src, size_t bytes) {
   return ESDG_OK;
 }
 
-esdg_status launch(esdg_swe *s, const StageArgs &a, int ntiles) {
-  hipError_t e = launch_stage(s->fp64, a, ntiles, s->lds_bytes, s->stream);
+esdg_status launch(esdg_swe *s, const StageArgs &a, int /*ntiles*/) {
+  hipError_t e = launch_stage(s->fp64, a, s->max_blocks, s->lds_bytes, s->stream);
   if (e != hipSuccess) return s->hip_fail(e, "stage kernel launch");
   return ESDG_OK;
 }
@@ -150,6 +154,7 @@ StageArgs base_args(esdg_swe *s, int inst) {
     a.ntiles = s->tile_count[inst];
   }
   a.flag = s->dev<int32_t>(s->flag_off);
+  a.ref_words_max = s->ref_max;
   return a;
 }
 
@@ -257,14 +262,16 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
       return ESDG_EINVAL;
     }
   }
-  // elements per workgroup and LDS
-  size_t lds = 0;
+  // elements per workgroup and LDS: the largest reference block + the largest tile
+  size_t tile = 0;
   for (auto &kv : s->refs) {
     const int N = kv.first;
     int E = opt->elems_per_block ? opt->elems_per_block : default_epb(N, s->word);
     s->epb[N] = E;
-    lds = std::max(lds, size_t(lds_words(N, E)) * s->word);
+    s->ref_max = std::max(s->ref_max, ref_words(N));
+    tile = std::max(tile, size_t(tile_words(N, E)));
   }
+  size_t lds = (size_t(s->ref_max) + tile) * s->word;
   if (lds > 160 * 1024) {
     g_init_error = "esdg_swe_init: elems_per_block needs more than 160 KiB of LDS";
     return ESDG_EINVAL;
@@ -324,6 +331,10 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
   if (s->lds_bytes > 64 * 1024) {
     hipError_t e = set_stage_lds_limit(s->fp64, s->lds_bytes);
     if (e != hipSuccess) return s->hip_fail(e, "hipFuncSetAttribute (LDS)");
+  }
+  {
+    hipError_t e = stage_max_blocks(s->fp64, s->lds_bytes, &s->max_blocks);
+    if (e != hipSuccess) return s->hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
   }
   esdg_status st;
   // host staging buffers stay alive until the stream is synchronised below
