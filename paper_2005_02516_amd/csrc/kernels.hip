@@ -147,54 +147,73 @@ __device__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L,
   if (bad) atomicOr(flag, 1);
 }
 
-// Phase 0: fetch the tile's global data into LDS.
+// Asynchronous global -> LDS copies (global_load_lds_dword): each lane moves one 32-bit
+// word straight into LDS at (wave-uniform base) + 4 * lane, so a wave copies 64
+// consecutive words per instruction without staging them in registers; completion is
+// awaited once, with s_waitcnt vmcnt(0), before the tile's barrier.
+typedef __attribute__((address_space(1))) const void *gptr_t;
+typedef __attribute__((address_space(3))) void *lptr_t;
+
+__device__ inline void async_copy_words(uint32_t *dst, const uint32_t *src, int nwords) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  for (int c = wave * 64; c < nwords; c += nwaves * 64) {
+    if (c + lane < nwords)
+      __builtin_amdgcn_global_load_lds((gptr_t)(src + c + lane), (lptr_t)(dst + c), 4, 0, 0);
+  }
+}
+
+// Phase 0: fetch the tile's global data into LDS (all asynchronous; see above).
 template <typename real, int N>
 __device__ void fetch_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, Lds<real, N> &L) {
   constexpr int Np = dim_Np(N), Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
-  const int tid = threadIdx.x, nth = blockDim.x;
+  constexpr int W = sizeof(real) / 4;     // 32-bit words per value
   const size_t plane = size_t(d.K) * Nh, splane = size_t(d.K) * Np;
+  auto words = [](const void *p) { return static_cast<const uint32_t *>(p); };
+  auto lwords = [](real *p) { return reinterpret_cast<uint32_t *>(p); };
   if (a.mode != kProject) {
     const real *ut = static_cast<const real *>(d.ut[a.in_buf]);
     const real *geo = static_cast<const real *>(d.geo);
     const size_t base = size_t(k0) * Nh;
-    for (int i = tid; i < ne * Nh; i += nth) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        L.raw[c * ne * Nh + i] = ut[c * plane + base + i];
-        L.raw[(4 + c) * ne * Nh + i] = geo[c * plane + base + i];
-      }
-    }
-    const int32_t *mapP = d.mapP + size_t(k0) * Nfq;
-    for (int i = tid; i < ne * Nfq; i += nth) {
-      const int32_t p = mapP[i];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) L.nb[i * 4 + c] = ut[c * plane + p];
+    for (int c = 0; c < 4; ++c) {
+      async_copy_words(lwords(L.raw + c * ne * Nh), words(ut + c * plane + base), ne * Nh * W);
+      async_copy_words(lwords(L.raw + (4 + c) * ne * Nh), words(geo + c * plane + base), ne * Nh * W);
     }
   }
   if (a.mode == kStage) {
     const real *uh = static_cast<const real *>(d.uh);
     const real *du = static_cast<const real *>(d.du);
-    for (int i = tid; i < ne * Np; i += nth) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        L.U[c * ne * Np + i] = uh[c * splane + size_t(k0) * Np + i];
-        L.DU[c * ne * Np + i] = du[c * splane + size_t(k0) * Np + i];
+    for (int c = 0; c < 3; ++c) {
+      async_copy_words(lwords(L.U + c * ne * Np), words(uh + c * splane + size_t(k0) * Np), ne * Np * W);
+      async_copy_words(lwords(L.DU + c * ne * Np), words(du + c * splane + size_t(k0) * Np), ne * Np * W);
+    }
+  } else if (a.mode == kProject) {
+    const real *src = static_cast<const real *>(a.ext_state ? a.ext_state : d.uh);
+    for (int c = 0; c < 3; ++c)
+      async_copy_words(lwords(L.U + c * ne * Np), words(src + c * splane + size_t(k0) * Np), ne * Np * W);
+  }
+  async_copy_words(lwords(L.Minv), words(static_cast<const real *>(d.Minv) + size_t(k0) * Np * Np), ne * Np * Np * W);
+  async_copy_words(lwords(L.wJ), words(static_cast<const real *>(d.wJq) + size_t(k0) * Nq), ne * Nq * W);
+  async_copy_words(lwords(L.bq), words(static_cast<const real *>(d.bq) + size_t(k0) * Nq), ne * Nq * W);
+  async_copy_words(lwords(L.bh), words(static_cast<const real *>(d.bh) + size_t(k0) * Nh), ne * Nh * W);
+  if (a.mode != kProject) {
+    // neighbour values: LDS word j of nb[(e*Nfq + f)*4 + c] comes from plane c at mapP
+    const uint32_t *ut = words(d.ut[a.in_buf]);
+    const int32_t *mapP = d.mapP + size_t(k0) * Nfq;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int nwords = ne * Nfq * 4 * W;
+    uint32_t *dst = lwords(L.nb);
+    for (int c0 = wave * 64; c0 < nwords; c0 += nwaves * 64) {
+      const int j = c0 + lane;
+      if (j < nwords) {
+        const int i = j / (4 * W), c = (j / W) % 4, w = j % W;
+        const size_t src = (size_t(c) * plane + size_t(mapP[i])) * W + w;
+        __builtin_amdgcn_global_load_lds((gptr_t)(ut + src), (lptr_t)(dst + c0), 4, 0, 0);
       }
     }
   }
-  const real *Minv = static_cast<const real *>(d.Minv) + size_t(k0) * Np * Np;
-  for (int i = tid; i < ne * Np * Np; i += nth) L.Minv[i] = Minv[i];
-  const real *wJ = static_cast<const real *>(d.wJq) + size_t(k0) * Nq;
-  const real *bq = static_cast<const real *>(d.bq) + size_t(k0) * Nq;
-  for (int i = tid; i < ne * Nq; i += nth) {
-    L.wJ[i] = wJ[i];
-    L.bq[i] = bq[i];
-  }
-  const real *bh = static_cast<const real *>(d.bh) + size_t(k0) * Nh;
-  for (int i = tid; i < ne * Nh; i += nth) L.bh[i] = bh[i];
+  __builtin_amdgcn_s_waitcnt(0);   // this wave's copies have landed in LDS
 }
 
-// Phase 2+3: residual rows, R rows of one element per thread.
 template <typename real, int N, int R, bool FACE>
 __device__ inline void row_block(const InstDesc &d, int ne, int e, int b, Lds<real, N> &L) {
   constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
@@ -300,12 +319,6 @@ __device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
   const real g = real(d.g);
   fetch_tile<real, N>(a, d, k0, ne, L);
   if (a.mode == kProject) {
-    const real *src = static_cast<const real *>(a.ext_state ? a.ext_state : d.uh);
-    const size_t splane = size_t(d.K) * Np;
-    for (int i = tid; i < 3 * ne * Np; i += nth) {
-      const int c = i / (ne * Np), r = i - c * ne * Np;
-      L.U[i] = src[c * splane + size_t(k0) * Np + r];
-    }
     __syncthreads();
     project_tile<real, N>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]), a.flag);
     return;
