@@ -62,11 +62,20 @@ struct Lds {
     bh = bq + E * Nq;
     // reuse: residual and lift temporaries live in the raw block (dead after phase 1),
     // the projection's pointwise values in the record block (dead after phase 2)
-    R = raw;
-    T = raw + 3 * E * Nh;
+    R = raw;                      // up to two partial residuals [2][3][E][Nh]
+    T = raw + 6 * E * Nh;
     Q = rec;
   }
 };
+
+// Rows per thread in the residual phase, per degree (must divide Nq and Nfq).
+template <int N> struct RowsPerThread { static constexpr int value = 1; };
+template <> struct RowsPerThread<1> { static constexpr int value = 2; };
+template <> struct RowsPerThread<3> { static constexpr int value = 2; };
+template <> struct RowsPerThread<5> { static constexpr int value = 3; };
+
+// Column parts of the residual phase, per degree (1 or 2).
+template <int N> struct ColParts { static constexpr int value = 2; };
 
 // Entropy projection of the tile states in L.U ([3][ne][Np]: eta, hu, hv) to the
 // hybridized nodes (Section 2.5), written to out ([4][K][Nh]: h~, u~, v~, H~ - Href):
@@ -106,10 +115,14 @@ __device__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L,
   for (int i = tid; i < 3 * ne * Np; i += nth) {
     const int c = i / (ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
     const real *Qc = L.Q + c * ne * Nq + e * Nq;
-    real y = 0;
+    real ya = 0, yb = 0;
 #pragma unroll 4
-    for (int q = 0; q < Nq; ++q) y += L.Vh[q * Np + j] * Qc[q];
-    L.T[i] = y;
+    for (int q = 0; q + 1 < Nq; q += 2) {
+      ya += L.Vh[q * Np + j] * Qc[q];
+      yb += L.Vh[(q + 1) * Np + j] * Qc[q + 1];
+    }
+    if (Nq & 1) ya += L.Vh[(Nq - 1) * Np + j] * Qc[Nq - 1];
+    L.T[i] = ya + yb;
   }
   __syncthreads();
   // v'_h = Minv_k y
@@ -117,10 +130,14 @@ __device__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L,
     const int c = i / (ne * Np), r = i - c * ne * Np, e = r / Np, row = r - e * Np;
     const real *Mi = L.Minv + (e * Np + row) * Np;
     const real *Tc = L.T + c * ne * Np + e * Np;
-    real v = 0;
+    real va = 0, vb = 0;
 #pragma unroll 4
-    for (int j = 0; j < Np; ++j) v += Mi[j] * Tc[j];
-    L.U[i] = v;
+    for (int j = 0; j + 1 < Np; j += 2) {
+      va += Mi[j] * Tc[j];
+      vb += Mi[j + 1] * Tc[j + 1];
+    }
+    if (Np & 1) va += Mi[Np - 1] * Tc[Np - 1];
+    L.U[i] = va + vb;
   }
   __syncthreads();
   const size_t plane = size_t(K) * Nh;
@@ -214,12 +231,13 @@ __device__ void fetch_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
   __builtin_amdgcn_s_waitcnt(0);   // this wave's copies have landed in LDS
 }
 
-template <typename real, int N, int R, bool FACE>
-__device__ inline void row_block(const InstDesc &d, int ne, int e, int b, Lds<real, N> &L) {
+template <typename real, int N, int R, int P, bool FACE>
+__device__ inline void row_block(const InstDesc &d, int ne, int e, int b, int p, Lds<real, N> &L) {
   constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
   // volume rows: all Nh columns (the diagonal of the skew operator is zero);
   // face rows: the Nq volume columns (the surface-surface block is zero)
   constexpr int NCOL = FACE ? Nq : Nh;
+  const int n_lo = p * NCOL / P, n_hi = (p + 1) * NCOL / P;   // this task's column range
   constexpr int LD = FACE ? Nfq : Nq;
   const int r0 = b * R;                       // first row within the row set
   const int m0 = FACE ? Nq + r0 : r0;         // first hybrid-node index
@@ -235,7 +253,7 @@ __device__ inline void row_block(const InstDesc &d, int ne, int e, int b, Lds<re
     a0[r] = 0; a1[r] = 0; a2[r] = 0;
   }
 #pragma unroll 2
-  for (int n = 0; n < NCOL; ++n) {
+  for (int n = n_lo; n < n_hi; ++n) {
     const real *rn = rbase + n * kNodeRec;
     const real hun = rn[0], hvn = rn[1], un = rn[2], vn = rn[3], dHn = rn[5];
     const real rxn = rn[6], sxn = rn[7], ryn = rn[8], syn = rn[9];
@@ -255,7 +273,7 @@ __device__ inline void row_block(const InstDesc &d, int ne, int e, int b, Lds<re
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int m = m0 + r;
-    if (FACE) {
+    if (FACE && p == 0) {
       // interface flux W_f [ nJ . f_S(u~, u~+) + 1/2 g h (H+ - Href) nJ ] - LF penalty
       const int f = r0 + r;
       const real *rm = rbase + m * kNodeRec;
@@ -263,8 +281,8 @@ __device__ inline void row_block(const InstDesc &d, int ne, int e, int b, Lds<re
       const real nJx = rx[r] * nrf + sx[r] * nsf, nJy = ry[r] * nrf + sy[r] * nsf;
       const real h = rm[10], uu = real(2) * u[r], vv = real(2) * v[r], dH = rm[5];
       const real huu = real(2) * hu[r], hvv = real(2) * hv[r];
-      const real *P = L.nb + (e * Nfq + f) * 4;
-      const real hP = P[0], uP = P[1], vP = P[2], dHP = P[3];
+      const real *nbp = L.nb + (e * Nfq + f) * 4;
+      const real hP = nbp[0], uP = nbp[1], vP = nbp[2], dHP = nbp[3];
       const real huP = hP * uP, hvP = hP * vP;
       const real hua = real(0.5) * (huu + huP), hva = real(0.5) * (hvv + hvP);
       const real ua = real(0.5) * (uu + uP), va = real(0.5) * (vv + vP);
@@ -285,28 +303,31 @@ __device__ inline void row_block(const InstDesc &d, int ne, int e, int b, Lds<re
       a1[r] += wf * f1v;
       a2[r] += wf * f2v;
     }
-    L.R[0 * ne * Nh + e * Nh + m] = a0[r];
-    L.R[1 * ne * Nh + e * Nh + m] = a1[r];
-    L.R[2 * ne * Nh + e * Nh + m] = a2[r];
+    real *Rp = L.R + p * 3 * ne * Nh;     // partial sums of column part p
+    Rp[0 * ne * Nh + e * Nh + m] = a0[r];
+    Rp[1 * ne * Nh + e * Nh + m] = a1[r];
+    Rp[2 * ne * Nh + e * Nh + m] = a2[r];
   }
 }
 
-// Phase 2+3: residual rows.  One flat task list: first every volume row block of every
-// element, then every face row block, so whole waves take the same branch.
-template <typename real, int N, int R>
+// Phase 2+3: residual rows.  A task is (element, block of R rows, column part p of P);
+// the P partial sums are added in the lift.  One flat task list: first every volume
+// task, then every face task, so whole waves take the same branch.
+template <typename real, int N, int R, int P>
 __device__ void residual_tile(const InstDesc &d, int ne, Lds<real, N> &L) {
   constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N);
   constexpr int VB = Nq / R, FB = Nfq / R;
   static_assert(Nq % R == 0 && Nfq % R == 0, "R must divide Nq and Nfq");
+  static_assert(6 * dim_Nh(N) + 3 * dim_Np(N) <= 8 * dim_Nh(N) || P == 1, "partials must fit the raw block");
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int nv = ne * VB, ntask = nv + ne * FB;
+  const int nv = ne * VB * P, ntask = nv + ne * FB * P;
   for (int t = tid; t < ntask; t += nth) {
     if (t < nv) {
-      const int e = t / VB;
-      row_block<real, N, R, false>(d, ne, e, t - e * VB, L);
+      const int p = t % P, rest = t / P, e = rest / VB;
+      row_block<real, N, R, P, false>(d, ne, e, rest - e * VB, p, L);
     } else {
-      const int tf = t - nv, e = tf / FB;
-      row_block<real, N, R, true>(d, ne, e, tf - e * FB, L);
+      const int tf = t - nv, p = tf % P, rest = tf / P, e = rest / FB;
+      row_block<real, N, R, P, true>(d, ne, e, rest - e * FB, p, L);
     }
   }
 }
@@ -341,16 +362,20 @@ __device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
     rec[10] = h;
   }
   __syncthreads();
-  residual_tile<real, N, R>(d, ne, L);
+  residual_tile<real, N, R, ColParts<N>::value>(d, ne, L);
   __syncthreads();
-  // lift: y = V_h^T r_h, one task per (field, element, mode)
+  // lift: y = V_h^T r_h (r_h = sum of the P partials), one task per (field, element, mode)
   for (int i = tid; i < 3 * ne * Np; i += nth) {
     const int c = i / (ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
     const real *Rc = L.R + c * ne * Nh + e * Nh;
-    real y = 0;
+    real ya = 0, yb = 0;
 #pragma unroll 4
-    for (int n = 0; n < Nh; ++n) y += L.Vh[n * Np + j] * Rc[n];
-    L.T[i] = y;
+    for (int n = 0; n < Nh; ++n) {
+      real rn = Rc[n];
+      if (ColParts<N>::value > 1) rn += Rc[3 * ne * Nh + n];
+      if (n & 1) yb += L.Vh[n * Np + j] * rn; else ya += L.Vh[n * Np + j] * rn;
+    }
+    L.T[i] = ya + yb;
   }
   __syncthreads();
   // rhs = -Minv y; store it, or do the LSRK update
@@ -393,8 +418,7 @@ __device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
   }
 }
 
-// Rows per thread in the residual phase, per degree (must divide Nq and Nfq).
-template <int N> struct RowsPerThread { static constexpr int value = 1; };
+
 
 // Persistent stage kernel: block b walks a contiguous range of tiles.  Blocks are dealt
 // to the XCDs round-robin, so block b's range is chosen as range number

@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -335,6 +337,12 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
   {
     hipError_t e = stage_max_blocks(s->fp64, s->lds_bytes, &s->max_blocks);
     if (e != hipSuccess) return s->hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    if (std::getenv("ESDG_SWE_VERBOSE")) {
+      std::fprintf(stderr, "esdg_swe: %s, LDS %zu B per workgroup, %d resident workgroups, %zu tiles;",
+                   s->fp64 ? "fp64" : "fp32", s->lds_bytes, s->max_blocks, s->tiles.size());
+      for (auto &kv : s->epb) std::fprintf(stderr, " N=%d: %d elements/tile", kv.first, kv.second);
+      std::fprintf(stderr, "\n");
+    }
   }
   esdg_status st;
   // host staging buffers stay alive until the stream is synchronised below
