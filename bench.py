@@ -70,7 +70,7 @@ def time_steps(s, dt, steps, torch):
     return ev0.elapsed_time(ev1)
 
 
-def cpu_baseline(w, stages_budget=15):
+def cpu_baseline(w, stages_budget=75):
     """The FP64 oracle as it stands, timed on this host: `stages_budget` RK stages of the
     same workload (one RHS + axpy each), BLAS pinned to one thread."""
     from threadpoolctl import threadpool_limits
@@ -92,6 +92,49 @@ def cpu_baseline(w, stages_budget=15):
                       f"workload, dense FP64 numpy oracle, BLAS limited to 1 thread, {t:.1f} s"}
 
 
+def ensemble(args, torch):
+    """Batched ensemble: independent instances (K ~ U{2048..32768}, N ~ U{2,3,4}, seeded
+    bathymetry and Gaussian perturbations) advanced together, one launch per RK stage."""
+    from paper_2005_02516_amd import workloads as wl
+    from paper_2005_02516_amd.binding import EsdgSwe
+    t0 = time.perf_counter()
+    ws = wl.config4_instances(count=args.ensemble)
+    print(f"# ensemble: {len(ws)} instances, {sum(w.K for w in ws)} elements, built in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    dts = np.array([w.dt for w in ws])
+    dof = sum(w.K * dims(w.N)[0] for w in ws)
+    dof3 = sum(w.K * dims(w.N)[0] for w in ws if w.N == 3)
+    res = {}
+    for prec in ([args.precision] + ([] if args.no_fp64 else ["fp64"])):
+        t0 = time.perf_counter()
+        s = EsdgSwe(ws, precision=prec, flux="lf", g=1.0, use_graph=not args.no_graph)
+        for i, w in enumerate(ws):
+            s.set_state(i, w.u_nodes)
+        print(f"# {prec}: planned and set in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        s.step(dts, args.warmup)
+        s.sync()
+        ms = time_steps(s, dts, args.steps, torch)
+        s.sync()
+        res[prec] = ms
+        print(f"# {prec}: {ms / args.steps * 1e3:.1f} us/step, {ms / (5 * args.steps) * 1e3:.1f} us/stage",
+              file=sys.stderr, flush=True)
+        s.close()
+    t_stage = res[args.precision] * 1e-3 / (5 * args.steps)
+    out = {"metric": "DOF-updates/s per RK stage, batched ensemble (all instances, one launch per stage)",
+           "value": dof / t_stage, "unit": "DOF-updates/s per RK stage", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": res[args.precision] / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "f64",
+           "data": "synthetic",
+           "config": {"workload": f"ensemble of {len(ws)} periodic curved instances, K~U{{2048..32768}}, "
+                                  f"N~U{{2,3,4}}, LF flux, LSRK4(5)",
+                      "instances": len(ws), "elements": int(sum(w.K for w in ws)), "DOF": int(dof),
+                      "DOF_N3": int(dof3)}}
+    if "fp64" in res and args.precision != "fp64":
+        out["fp64_value"] = dof / (res["fp64"] * 1e-3 / (5 * args.steps))
+        out["speedup_vs_fp64"] = out["value"] / out["fp64_value"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +147,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--ensemble", type=int, default=0,
+                    help="time the batched ensemble of this many instances instead (256 = the full ensemble)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -125,6 +170,8 @@ def main():
     from paper_2005_02516_amd import workloads as wl
     from paper_2005_02516_amd.binding import EsdgSwe
 
+    if args.ensemble:
+        return ensemble(args, torch)
     w = wl.config2(n=args.n, N=args.N)
     Np, Nq, Nfq, Nh = dims(w.N)
     dof = w.K * Np

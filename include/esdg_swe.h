@@ -99,8 +99,9 @@ typedef struct {
   int32_t precision;        /* ESDG_FP64 | ESDG_FP32 | ESDG_FP32_BF16X3                      */
   int32_t flux;             /* ESDG_FLUX_EC | ESDG_FLUX_LF                                   */
   double g;                 /* gravitational constant, > 0                                    */
-  int32_t elems_per_block;  /* elements per workgroup; 0 = tuned default per N               */
   int32_t use_graph;        /* nonzero: esdg_swe_step replays HIP graphs of its RK stages    */
+  int32_t elems_per_block[6]; /* elements per workgroup for degree N = index (1..5); 0 = the
+                                 library's default for that degree; index 0 unused            */
 } esdg_swe_options;
 
 /* Plan a solver for n_inst independent instances (n_inst = 1 for a single run).  Builds,

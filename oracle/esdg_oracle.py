@@ -293,43 +293,41 @@ class Discretization:
     def _connect(self) -> np.ndarray:
         """mapP[k, f]: flat index k'*Nfq + f' of the neighbour's face node at the same point.
 
-        Faces are matched through the periodic images of their midpoints; nodes of two
-        matched faces are paired by coordinates.  Every node must find a partner.
+        Faces are paired by the periodic images of their midpoints (rounded to a fine grid,
+        then wrapped); the nodes of two paired faces are matched by nearest periodic
+        distance.  Every face must have exactly one partner and every node a partner
+        closer than the tolerance.
         """
         ref = self.ref
         K, Nfp, Nq = self.K, ref.Nfp, ref.Nq
-        xf = self.xh[:, Nq:].reshape(K, 3, Nfp)
-        yf = self.yh[:, Nq:].reshape(K, 3, Nfp)
-        L = np.array([self.Lx, self.Ly])
-        mid = np.stack([xf.mean(axis=2), yf.mean(axis=2)], axis=-1)          # K,3,2
-        hscale = float(np.max(np.abs(xf[:, :, -1] - xf[:, :, 0]) + np.abs(yf[:, :, -1] - yf[:, :, 0])))
+        xf = self.xh[:, Nq:].reshape(K * 3, Nfp)
+        yf = self.yh[:, Nq:].reshape(K * 3, Nfp)
+        hscale = float(np.max(np.hypot(xf[:, -1] - xf[:, 0], yf[:, -1] - yf[:, 0])))
         tol = 1e-7 * hscale
-        key = np.round((mid % L) / (1e-4 * hscale)).astype(np.int64)
-        key[:, :, 0] %= int(round(self.Lx / (1e-4 * hscale)))
-        key[:, :, 1] %= int(round(self.Ly / (1e-4 * hscale)))
-        table: Dict[Tuple[int, int], list] = {}
-        for k in range(K):
-            for fc in range(3):
-                table.setdefault((int(key[k, fc, 0]), int(key[k, fc, 1])), []).append((k, fc))
-        mapP = np.full((K, 3 * Nfp), -1, dtype=np.int64)
-        for k in range(K):
-            for fc in range(3):
-                cand = table[(int(key[k, fc, 0]), int(key[k, fc, 1]))]
-                others = [c for c in cand if c != (k, fc)]
-                if len(others) != 1:
-                    raise ValueError(f"face ({k},{fc}) has {len(others)} partners")
-                k2, f2 = others[0]
-                for i in range(Nfp):
-                    dx = xf[k2, f2, :] - xf[k, fc, i]
-                    dy = yf[k2, f2, :] - yf[k, fc, i]
-                    dx -= self.Lx * np.round(dx / self.Lx)
-                    dy -= self.Ly * np.round(dy / self.Ly)
-                    d = np.hypot(dx, dy)
-                    j = int(np.argmin(d))
-                    if d[j] > tol:
-                        raise ValueError(f"unmatched face node ({k},{fc},{i})")
-                    mapP[k, fc * Nfp + i] = k2 * 3 * Nfp + f2 * Nfp + j
-        return mapP
+        cell = 1e-4 * hscale
+        ncx = int(round(self.Lx / cell))
+        ncy = int(round(self.Ly / cell))
+        kx = np.round((xf.mean(axis=1) % self.Lx) / cell).astype(np.int64) % ncx
+        ky = np.round((yf.mean(axis=1) % self.Ly) / cell).astype(np.int64) % ncy
+        key = kx * ncy + ky
+        order = np.argsort(key, kind="stable")
+        ks = key[order]
+        if ks.size % 2 or np.any(ks[0::2] != ks[1::2]) or (ks.size > 2 and np.any(ks[2::2] == ks[1:-1:2])):
+            raise ValueError("every face needs exactly one periodic partner")
+        partner = np.empty(K * 3, dtype=np.int64)
+        partner[order[0::2]] = order[1::2]
+        partner[order[1::2]] = order[0::2]
+        # node matching: nearest node of the partner face, distances taken periodically
+        dx = xf[partner][:, None, :] - xf[:, :, None]
+        dy = yf[partner][:, None, :] - yf[:, :, None]
+        dx -= self.Lx * np.round(dx / self.Lx)
+        dy -= self.Ly * np.round(dy / self.Ly)
+        d = np.hypot(dx, dy)                                 # [face, my node, partner node]
+        j = np.argmin(d, axis=2)
+        if np.max(np.take_along_axis(d, j[:, :, None], axis=2)) > tol:
+            raise ValueError("unmatched face node")
+        mapP = partner[:, None] * Nfp + j                      # flat face-node index
+        return mapP.reshape(K, 3 * Nfp)
 
     # -- nodal <-> modal --------------------------------------------------------------
     def interpolate(self, u_nodes: np.ndarray) -> np.ndarray:

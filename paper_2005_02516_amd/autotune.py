@@ -1,0 +1,115 @@
+"""Autotuner for the elements-per-workgroup tile size of the RK-stage kernel.
+
+The stage kernel's LDS footprint, and so its occupancy, grows with the number of elements
+per workgroup E, while small E leaves threads idle in every phase; the best E depends on
+the degree N, the precision and how many elements there are in total.  ``tune`` times a
+few LSRK steps for every candidate E (HIP events on the solver's stream) and records the
+fastest in a JSON cache keyed by precision, N and a size class of the element count;
+``lookup`` reads it when a solver is created without an explicit tile size.
+
+Run ``python -m paper_2005_02516_amd.autotune --write`` on the GPU to refresh the cache.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+from typing import Dict, Iterable, List, Optional, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tune_cache_gfx950.json")
+CANDIDATES = (1, 2, 4, 8, 16, 32)
+
+
+def size_class(K: int) -> str:
+    """S: < 32768 elements, M: < 262144, L: larger."""
+    return "S" if K < 32768 else ("M" if K < 262144 else "L")
+
+
+def _key(precision: str, N: int, K: int) -> str:
+    return f"{precision}:N{N}:{size_class(K)}"
+
+
+def _load() -> dict:
+    if not os.path.exists(CACHE):
+        return {}
+    with open(CACHE) as f:
+        return json.load(f)
+
+
+def lookup(precision: str, sizes: Iterable[Tuple[int, int]]) -> Optional[Dict[int, int]]:
+    """Tuned E per degree for instances of (N, K); the total K of each degree picks the class."""
+    cache = _load().get("entries", {})
+    totals: Dict[int, int] = {}
+    for N, K in sizes:
+        totals[N] = totals.get(N, 0) + K
+    out = {}
+    for N, K in totals.items():
+        e = cache.get(_key(precision, N, K))
+        if e:
+            out[N] = int(e["epb"])
+    return out or None
+
+
+def time_config(w, precision: str, epb: int, steps: int = 4, warmup: int = 1) -> float:
+    """Milliseconds per RK stage for one workload at tile size epb."""
+    import torch
+    from .binding import EsdgSwe
+    s = EsdgSwe([w], precision=precision, flux=w.flux, g=w.g, elems_per_block=epb, tuned=False)
+    try:
+        s.set_state(0, w.u_nodes)
+        s.step(w.dt, warmup)
+        s.sync()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.step(w.dt, steps)
+        e1.record(s.stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / (5 * steps)
+    finally:
+        s.close()
+
+
+def lds_ok(N: int, E: int, precision: str) -> bool:
+    Np, Nq, Nfq = (N + 1) * (N + 2) // 2, (N + 1) ** 2, 3 * (N + 1)
+    Nh = Nq + Nfq
+    ref = Nh * Np + 2 * Nh * Nq + 2 * Nq * Nfq + 3 * Nfq
+    tile = E * (Nh * 11 + 8 * Nh + 4 * Nfq + 6 * Np + Np * Np + 2 * Nq + Nh)
+    word = 8 if precision == "fp64" else 4
+    return (ref + tile) * word <= 160 * 1024 and E * Nh <= 2048
+
+
+def tune(cases: List[Tuple[int, int]], precisions=("fp32", "fp64"), write: bool = True, log=sys.stderr):
+    from . import workloads as wl
+    data = _load()
+    entries = data.setdefault("entries", {})
+    for N, n in cases:
+        w = wl.config2(n=n, N=N)
+        for prec in precisions:
+            timings = {}
+            for E in CANDIDATES:
+                if not lds_ok(N, E, prec):
+                    continue
+                timings[E] = time_config(w, prec, E, steps=4 if w.K < 100000 else 2)
+                print(f"# tune {prec} N={N} K={w.K} E={E}: {timings[E] * 1e3:.1f} us/stage", file=log, flush=True)
+            best = min(timings, key=timings.get)
+            entries[_key(prec, N, w.K)] = {"epb": best, "K": w.K, "us_per_stage": {str(k): round(v * 1e3, 2)
+                                                                                      for k, v in timings.items()}}
+    data["device"] = "gfx950 (MI355X)"
+    data["note"] = "written by `python -m paper_2005_02516_amd.autotune --write` on the GPU"
+    if write:
+        with open(CACHE, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+    return data
+
+
+DEFAULT_CASES = [(1, 64), (2, 64), (3, 64), (4, 64), (5, 64), (2, 256), (3, 256), (4, 256), (5, 256)]
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--write", action="store_true")
+    args = ap.parse_args()
+    tune(DEFAULT_CASES, write=args.write)

@@ -35,7 +35,19 @@ class esdg_swe_instance(C.Structure):
 
 class esdg_swe_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("flux", C.c_int32), ("g", C.c_double),
-                ("elems_per_block", C.c_int32), ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("elems_per_block", C.c_int32 * 6)]
+
+
+def make_options(precision: str, flux: str, g: float, use_graph: bool = True, epb=None) -> esdg_swe_options:
+    """epb: None, an int (all degrees) or a mapping N -> elements per workgroup."""
+    arr = (C.c_int32 * 6)()
+    if isinstance(epb, int):
+        for N in range(1, 6):
+            arr[N] = epb
+    elif epb:
+        for N, E in epb.items():
+            arr[int(N)] = int(E)
+    return esdg_swe_options(PRECISIONS[precision], FLUXES[flux], float(g), int(use_graph), arr)
 
 
 class EsdgError(RuntimeError):
@@ -94,7 +106,8 @@ class EsdgSwe:
     """One solver handle for n_inst instances, bound to a torch-allocated workspace."""
 
     def __init__(self, instances: Sequence, precision: str = "fp64", flux: str = "lf", g: float = 1.0,
-                 elems_per_block: int = 0, use_graph: bool = True, device: str = "cuda:0", stream=None):
+                 elems_per_block=None, use_graph: bool = True, device: str = "cuda:0", stream=None,
+                 tuned: bool = True):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("EsdgSwe needs a GPU: the library has no CPU path")
@@ -109,7 +122,10 @@ class EsdgSwe:
             b = np.ascontiguousarray(w.b_nodes, dtype=np.float64)
             self._keep += [xg, yg, b]
             arr[i] = esdg_swe_instance(w.N, w.K, _dptr(xg), _dptr(yg), _dptr(b), w.Lx, w.Ly)
-        opt = esdg_swe_options(PRECISIONS[precision], FLUXES[flux], float(g), int(elems_per_block), int(use_graph))
+        if not elems_per_block and tuned:
+            from .autotune import lookup
+            elems_per_block = lookup(precision, [(w.N, w.K) for w in instances])
+        opt = make_options(precision, flux, g, use_graph, elems_per_block)
         h = C.c_void_p()
         nbytes = C.c_size_t()
         st = self.lib.esdg_swe_init(len(instances), arr, C.byref(opt), C.byref(h), C.byref(nbytes))

@@ -16,6 +16,13 @@ __host__ __device__ constexpr int dim_Nq(int N) { return (N + 1) * (N + 1); }
 __host__ __device__ constexpr int dim_Nfq(int N) { return 3 * (N + 1); }
 __host__ __device__ constexpr int dim_Nh(int N) { return dim_Nq(N) + dim_Nfq(N); }
 
+// Relative cost of one element of degree N in a stage (flux-differencing and contraction
+// flops), used to balance persistent workgroups over mixed-degree tile lists.
+__host__ __device__ constexpr long long elem_cost(int N) {
+  return 35LL * (dim_Nq(N) * (dim_Nq(N) - 1) / 2 + dim_Nq(N) * dim_Nfq(N)) +
+         6LL * (2 * dim_Nq(N) * dim_Np(N) + 2 * dim_Np(N) * dim_Np(N) + 2 * dim_Nh(N) * dim_Np(N));
+}
+
 // Reference-operator block of degree N, stored contiguously in the bulk precision:
 //   Vh [Nh][Np]
 //   ST [Nh][Nq][2]  ST[n][m] = (S^r[m][n], S^s[m][n]) for volume rows m (column-major
@@ -71,6 +78,8 @@ struct StageArgs {
   int32_t mode;
   int32_t ref_words_max;  // LDS words reserved for the reference block (largest degree)
   int32_t pad;
+  const int32_t *ranges;  // optional [grid+1]: tile range of each block's chunk (cost-balanced);
+                          // null means equal numbers of tiles per chunk
   int32_t in_buf, out_buf;
   double rk_a, rk_b;
   const void *ext_state;  // kProject: read this state instead of desc.uh (when non-null)

@@ -432,8 +432,8 @@ __global__ void __launch_bounds__(kBlock, 2) stage_kernel(StageArgs a) {
   real *tile = sm + a.ref_words_max;
   const int G = int(gridDim.x);
   const int chunk = (int(blockIdx.x) % kXcds) * (G / kXcds) + int(blockIdx.x) / kXcds;
-  const int t0 = int((long long)chunk * a.ntiles / G);
-  const int t1 = int((long long)(chunk + 1) * a.ntiles / G);
+  const int t0 = a.ranges ? a.ranges[chunk] : int((long long)chunk * a.ntiles / G);
+  const int t1 = a.ranges ? a.ranges[chunk + 1] : int((long long)(chunk + 1) * a.ntiles / G);
   int loaded_N = 0;
   for (int t = t0; t < t1; ++t) {
     const Tile tl = a.tiles[t];
@@ -543,6 +543,7 @@ hipError_t set_stage_lds_limit(bool fp64, size_t lds_bytes) {
 
 // Persistent grid: at most max_blocks (what stays resident), at most one block per tile,
 // always a whole number of XCD rounds (blocks whose range is empty just exit).
+int stage_grid(int ntiles, int max_blocks);
 int stage_grid(int ntiles, int max_blocks) {
   int g = ntiles < max_blocks ? ntiles : max_blocks;
   return ((g + kXcds - 1) / kXcds) * kXcds;

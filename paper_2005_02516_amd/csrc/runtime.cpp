@@ -21,6 +21,7 @@ namespace esdg {
 hipError_t set_stage_lds_limit(bool fp64, size_t lds_bytes);
 hipError_t launch_stage(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream);
 hipError_t stage_max_blocks(bool fp64, size_t lds_bytes, int *out);
+int stage_grid(int ntiles, int max_blocks);
 hipError_t launch_diag(bool fp64, const DiagArgs &a, hipStream_t stream);
 }  // namespace esdg
 
@@ -66,7 +67,8 @@ struct esdg_swe {
   std::vector<InstanceHost> host;
   std::vector<Offsets> off;
   std::map<int, size_t> ref_off;
-  size_t tiles_off = 0, desc_off = 0, flag_off = 0, partial_off = 0;
+  size_t tiles_off = 0, desc_off = 0, flag_off = 0, partial_off = 0, ranges_off = 0;
+  bool balanced = false;           // mixed degrees: cost-balanced tile ranges uploaded
   size_t ws_bytes = 0;
   std::map<int, int> epb;          // elements per workgroup per N
   size_t lds_bytes = 0;
@@ -151,6 +153,7 @@ StageArgs base_args(esdg_swe *s, int inst) {
   if (inst < 0) {
     a.tiles = s->dev<Tile>(s->tiles_off);
     a.ntiles = int(s->tiles.size());
+    a.ranges = s->balanced ? s->dev<int32_t>(s->ranges_off) : nullptr;
   } else {
     a.tiles = s->dev<Tile>(s->tiles_off) + s->tile_begin[inst];
     a.ntiles = s->tile_count[inst];
@@ -226,7 +229,7 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
   }
   *out = nullptr;
   if (opt->precision < ESDG_FP64 || opt->precision > ESDG_FP32_BF16X3 || opt->flux < 0 || opt->flux > 1 ||
-      !(opt->g > 0.0) || opt->elems_per_block < 0 || opt->elems_per_block > 64) {
+      !(opt->g > 0.0)) {
     g_init_error = "esdg_swe_init: option out of range";
     return ESDG_EINVAL;
   }
@@ -234,6 +237,11 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
     g_init_error = "esdg_swe_init: ESDG_FP32_BF16X3 is not available in this build";
     return ESDG_EINVAL;
   }
+  for (int N = 1; N <= kMaxN; ++N)
+    if (opt->elems_per_block[N] < 0 || opt->elems_per_block[N] > 64) {
+      g_init_error = "esdg_swe_init: elems_per_block out of range (0..64)";
+      return ESDG_EINVAL;
+    }
   std::unique_ptr<esdg_swe> s(new esdg_swe());
   s->n_inst = n_inst;
   s->opt = *opt;
@@ -268,7 +276,7 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
   size_t tile = 0;
   for (auto &kv : s->refs) {
     const int N = kv.first;
-    int E = opt->elems_per_block ? opt->elems_per_block : default_epb(N, s->word);
+    int E = opt->elems_per_block[N] ? opt->elems_per_block[N] : default_epb(N, s->word);
     s->epb[N] = E;
     s->ref_max = std::max(s->ref_max, ref_words(N));
     tile = std::max(tile, size_t(tile_words(N, E)));
@@ -316,6 +324,7 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
   s->desc_off = take(n_inst * sizeof(InstDesc));
   s->flag_off = take(256);
   s->partial_off = take(s->tiles.size() * 6 * sizeof(double));
+  s->ranges_off = take((s->tiles.size() + 16) * sizeof(int32_t));
   s->ws_bytes = o;
   s->desc.resize(n_inst);
   s->state_set.assign(n_inst, false);
@@ -386,6 +395,24 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
   }
   if ((st = upload(s, s->desc_off, s->desc.data(), s->desc.size() * sizeof(InstDesc)))) return st;
   if ((st = upload(s, s->tiles_off, s->tiles.data(), s->tiles.size() * sizeof(Tile)))) return st;
+  // mixed degrees: split the tile list into contiguous chunks of equal estimated cost
+  std::vector<int32_t> ranges;
+  if (s->refs.size() > 1) {
+    const int G = stage_grid(int(s->tiles.size()), s->max_blocks);
+    std::vector<long long> cum(s->tiles.size() + 1, 0);
+    for (size_t t = 0; t < s->tiles.size(); ++t)
+      cum[t + 1] = cum[t] + elem_cost(s->host[s->tiles[t].inst].N) * s->tiles[t].ne;
+    ranges.resize(G + 1);
+    size_t t = 0;
+    for (int c = 0; c <= G; ++c) {
+      const long long target = (long long)((__int128)cum.back() * c / G);
+      while (t < s->tiles.size() && cum[t] < target) ++t;
+      ranges[c] = int32_t(t);
+    }
+    ranges[G] = int32_t(s->tiles.size());
+    if ((st = upload(s, s->ranges_off, ranges.data(), ranges.size() * sizeof(int32_t)))) return st;
+    s->balanced = true;
+  }
   hipError_t e = hipMemsetAsync(s->ws + s->flag_off, 0, 256, s->stream);
   if (e != hipSuccess) return s->hip_fail(e, "hipMemsetAsync (flag)");
   e = hipStreamSynchronize(s->stream);

@@ -94,19 +94,15 @@ def structured_mesh(n: int, N: int, L: float = 2.0, warp: float = 0.0, x0: float
     ij = equispaced_index(N)
     M = n * N
     hl = L / M
-    Ilist = []
-    Jlist = []
-    for jq in range(n):
-        for iq in range(n):
-            bi, bj = iq * N, jq * N
-            # lower triangle: v1=p00, v2=p10, v3=p11  -> lattice (bi + i + j, bj + j)
-            Ilist.append(bi + ij[:, 0] + ij[:, 1])
-            Jlist.append(bj + ij[:, 1])
-            # upper triangle: v1=p00, v2=p11, v3=p01  -> lattice (bi + i, bj + i + j)
-            Ilist.append(bi + ij[:, 0])
-            Jlist.append(bj + ij[:, 0] + ij[:, 1])
-    I = np.array(Ilist)
-    J = np.array(Jlist)
+    # squares in the order (jq, iq) row-major; each gives its lower then its upper triangle
+    jq, iq = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    bi = (iq.reshape(-1) * N)[:, None]
+    bj = (jq.reshape(-1) * N)[:, None]
+    i_, j_ = ij[None, :, 0], ij[None, :, 1]
+    # lower triangle: v1=p00, v2=p10, v3=p11  -> lattice (bi + i + j, bj + j)
+    # upper triangle: v1=p00, v2=p11, v3=p01  -> lattice (bi + i, bj + i + j)
+    I = np.stack([bi + i_ + j_, bi + i_], axis=1).reshape(-1, ij.shape[0])
+    J = np.stack([bj + j_, bj + i_ + j_], axis=1).reshape(-1, ij.shape[0])
 
     def place(Ii, Jj):
         x = x0 + Ii * hl

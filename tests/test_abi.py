@@ -33,7 +33,10 @@ def _init(lib, w, precision=1, flux=1, g=1.0, epb=0, xg=None):
     b = np.ascontiguousarray(w.b_nodes)
     arr = (binding.esdg_swe_instance * 1)()
     arr[0] = binding.esdg_swe_instance(w.N, w.K, binding._dptr(xg), binding._dptr(yg), binding._dptr(b), w.Lx, w.Ly)
-    opt = binding.esdg_swe_options(precision, flux, g, epb, 1)
+    opt = binding.make_options({0: "fp64", 1: "fp32"}.get(precision, "fp32") if precision in (0, 1) else "fp32",
+                               {0: "ec", 1: "lf"}[flux], g, True, epb)
+    if precision not in (0, 1):
+        opt.precision = precision
     h = C.c_void_p()
     nb = C.c_size_t()
     st = lib.esdg_swe_init(1, arr, C.byref(opt), C.byref(h), C.byref(nb))
