@@ -8,9 +8,9 @@
  * acceleration", arXiv 2005.02516.
  *
  *   rhs = -(M_h^k)^{-1} V_h^T r_h, where r_h is the hybridized-node residual of the
- *   semi-discrete form eq. (dgform) (Section 2.7): entropy projection (Section 2.5),
+ *   semi-discrete form eq. (dgform) (Section 2.8): entropy projection (Section 2.6),
  *   flux differencing with the hybridized SBP operators and the entropy-conservative
- *   SWE flux on curved elements (Sections 2.3, 2.6, 2.7), bathymetry source, interface
+ *   SWE flux on curved elements (Sections 2.3, 2.7, 2.8), bathymetry source, interface
  *   flux with optional local Lax-Friedrichs penalty (Section 2.8), and the
  *   per-element inverse curved mass matrix.  Time stepping: the 2N-storage
  *   Carpenter-Kennedy RK4(5) named in Section 4.
@@ -77,7 +77,7 @@ enum {
                            three bf16 products (hi*hi + hi*lo + lo*hi) accumulated in float */
 };
 
-/* interface flux (Section 2.7 / 2.8) */
+/* interface flux (Section 2.8) */
 enum {
   ESDG_FLUX_EC = 0,     /* entropy-conservative flux, no dissipation                        */
   ESDG_FLUX_LF = 1      /* plus local Lax-Friedrichs penalty on entropy-projected variables */
@@ -107,7 +107,7 @@ typedef struct {
 /* Plan a solver for n_inst independent instances (n_inst = 1 for a single run).  Builds,
  * on the host in double precision, the reference operators of each degree, the
  * isoparametric geometry, the periodic face connectivity and the inverse curved mass
- * matrices (Sections 2.1-2.6).  Validates: 1 <= N <= 5, J > 0 at every quadrature node,
+ * matrices (Sections 2.1-2.7).  Validates: 1 <= N <= 5, J > 0 at every quadrature node,
  * every face node matched.  On success *out is a new handle and *workspace_bytes the
  * device workspace size esdg_swe_bind needs.  No device call is made. */
 esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const esdg_swe_options *opt,

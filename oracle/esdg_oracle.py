@@ -10,7 +10,7 @@ Source: Wu, Kubatko & Chan, "High-order entropy stable discontinuous Galerkin
 methods for the shallow water equations: curved triangular meshes and GPU
 acceleration" (arXiv 2005.02516).  Every function names the section / equation it
 follows.  It evaluates the *literal dense* semi-discrete form, eq. (dgform) of
-Section 2.7, with the Lax-Friedrichs penalty of Section 2.8 and the five-stage
+Section 2.8, with the Lax-Friedrichs penalty of Section 2.8 and the five-stage
 low-storage RK4 of Section 4, in float64, vectorised over elements with numpy.
 
 Readings where the paper is silent, garbled or ambiguous (all listed in the design doc):
@@ -21,11 +21,11 @@ Readings where the paper is silent, garbled or ambiguous (all listed in DESIGN.m
   (N+1)^2 points (exact to degree 2N+1) and N+1 Gauss-Legendre points per face;
 * reference vertices taken counter-clockwise (-1,-1), (1,-1), (-1,1); face 1 is
   s=-1, face 2 is r+s=0, face 3 is r=-1, each parametrised counter-clockwise;
-* geometric factors G_ij (Section 2.6) are the Jacobian-scaled cofactors
+* geometric factors G_ij (Section 2.7) are the Jacobian-scaled cofactors
   rxJ = y_s, sxJ = -y_r, ryJ = -x_s, syJ = x_r, so that
   B^{i,k} = W_f diag(nJ_i) with nJ = G * nhat;
 * entropy projection on curved elements uses the J-weighted L2 projection
-  (M_h^k)^{-1} V_q^T W diag(J) (Section 2.5 with the curved mass matrix of Section 2.6);
+  (M_h^k)^{-1} V_q^T W diag(J) (Section 2.6 with the curved mass matrix of Section 2.7);
 * the flux matrix is F^i[m, n] = f_S^i(u~_m, u~_n) over all hybridized nodes;
 * the bathymetry source is -g V_h^T [0; diag(h~) Q_h^{x,k} b; diag(h~) Q_h^{y,k} b]
   with b evaluated at the hybridized nodes (the y-momentum source uses b_y);
@@ -233,7 +233,7 @@ class ReferenceElement:
 
 
 # ----------------------------------------------------------------------------------
-# Mesh geometry and connectivity (Section 2.6)
+# Mesh geometry and connectivity (Section 2.7)
 # ----------------------------------------------------------------------------------
 
 
@@ -362,7 +362,7 @@ class Discretization:
 
 
 # ----------------------------------------------------------------------------------
-# Shallow-water entropy, entropy variables and fluxes (Sections 2.4, 2.7)
+# Shallow-water entropy, entropy variables and fluxes (Sections 2.4, 2.8)
 # ----------------------------------------------------------------------------------
 
 
@@ -393,7 +393,7 @@ def physical_flux(h, hu, hv, g):
 
 
 def ec_flux(uL, uR, g):
-    """Entropy-conservative fluxes f^x_S, f^y_S of Section 2.7 with arithmetic averages {.}.
+    """Entropy-conservative fluxes f^x_S, f^y_S of Section 2.8 with arithmetic averages {.}.
 
     uL, uR are tuples (h, hu, hv) of broadcastable arrays.
     """
@@ -413,7 +413,7 @@ def ec_flux(uL, uR, g):
 
 
 # ----------------------------------------------------------------------------------
-# Semi-discrete right-hand side (Sections 2.5-2.8), literal dense form
+# Semi-discrete right-hand side (Sections 2.6-2.8), literal dense form
 # ----------------------------------------------------------------------------------
 
 
@@ -427,7 +427,7 @@ class Oracle:
         self.flux = flux
         self.chunk = chunk
 
-    # Section 2.5: entropy projection
+    # Section 2.6: entropy projection
     def entropy_projection(self, uh: np.ndarray):
         """u_q = V_q u_h, v_q = v(u_q), v_h = P^k v_q, v~ = V_h v_h, u~ = u(v~).
 
@@ -442,7 +442,7 @@ class Oracle:
         return ut, vh
 
     def physical_Qh(self, ks):
-        """Q_h^{i,k}[m,n] = 1/2 sum_j (G_ij[m] + G_ij[n]) Qhat_h^j[m,n] (Section 2.6)."""
+        """Q_h^{i,k}[m,n] = 1/2 sum_j (G_ij[m] + G_ij[n]) Qhat_h^j[m,n] (Section 2.7)."""
         d, ref = self.d, self.d.ref
         Qr, Qs = ref.Qh
         def op(Gr, Gs):

@@ -45,10 +45,13 @@ def lookup(precision: str, sizes: Iterable[Tuple[int, int]]) -> Optional[Dict[in
     for N, K in sizes:
         totals[N] = totals.get(N, 0) + K
     out = {}
+    order = {"S": ("S", "M", "L"), "M": ("M", "L", "S"), "L": ("L", "M", "S")}
     for N, K in totals.items():
-        e = cache.get(_key(precision, N, K))
-        if e:
-            out[N] = int(e["epb"])
+        for cls in order[size_class(K)]:        # nearest tuned size class
+            e = cache.get(f"{precision}:N{N}:{cls}")
+            if e:
+                out[N] = int(e["epb"])
+                break
     return out or None
 
 

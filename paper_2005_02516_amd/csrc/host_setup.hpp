@@ -37,7 +37,7 @@ struct RefElem {
 
 RefElem build_ref(int N);
 
-// Per-instance host data produced from the caller's mesh (Section 2.6).
+// Per-instance host data produced from the caller's mesh (Section 2.7).
 struct InstanceHost {
   int N = 0, K = 0;
   double Lx = 0, Ly = 0;

@@ -9,15 +9,15 @@
 //   2. flux differencing in skew form (Section 5.2, Step 4): every row m of every
 //      nonzero block of Q_skew = Q_h - Q_h^T (volume-volume and volume-surface; the zero
 //      surface-surface block is skipped), with the element's physical operator built on
-//      the fly from averaged geometric factors (Section 2.6) and the EC flux of
-//      Section 2.7; each thread owns R rows of one element so a column's node record is
+//      the fly from averaged geometric factors (Section 2.7) and the EC flux of
+//      Section 2.8; each thread owns R rows of one element so a column's node record is
 //      read once for R rows.  The bathymetry source is folded in as
 //      1/2 g h_m (H_n - Href) Q_mn (exact because Q_h 1 = 0);
 //   3. interface flux f_S(u~+, u~), boundary half of the source and optional local
 //      Lax-Friedrichs penalty (Section 2.8) on the face rows;
-//   4. lift rhs = -(M_h^k)^{-1} V_h^T r_h with the stored inverses (Section 2.7);
+//   4. lift rhs = -(M_h^k)^{-1} V_h^T r_h with the stored inverses (Section 2.8);
 //   5. LSRK update (Section 4), then, fused, the entropy projection of the updated state
-//      (Section 2.5) written to the other stage buffer for the next stage.
+//      (Section 2.6) written to the other stage buffer for the next stage.
 // The launch boundary is the grid-wide barrier the neighbour gather needs.
 //
 // Depth is carried as the free-surface anomaly eta = h + b - Href (Href a per-instance
@@ -78,7 +78,7 @@ template <> struct RowsPerThread<5> { static constexpr int value = 3; };
 template <int N> struct ColParts { static constexpr int value = 2; };
 
 // Entropy projection of the tile states in L.U ([3][ne][Np]: eta, hu, hv) to the
-// hybridized nodes (Section 2.5), written to out ([4][K][Nh]: h~, u~, v~, H~ - Href):
+// hybridized nodes (Section 2.6), written to out ([4][K][Nh]: h~, u~, v~, H~ - Href):
 //   q = V_q u_h; h = eta_q + Href - b_q; v' = (g eta_q - |u|^2/2, u, v) = v(u_q) - (g Href, 0, 0)
 //   (FP64); v'_h = Minv_k V_q^T diag(w J) v'_q; v~' = V_h v'_h;
 //   H~ - Href = (v~1' + |v~23|^2/2)/g, h~ = Href + (H~ - Href) - b~ (FP64).

@@ -1,9 +1,9 @@
 """Pins of the oracle's discretisation against what the paper and the mathematics fix.
 
 * geometry: J > 0, affine elements give constant J, discrete GCL / physical SBP
-  (Section 2.6), watertight periodic matching, total area;
+  (Section 2.7), watertight periodic matching, total area;
 * flux: consistency, symmetry and Tadmor's entropy-conservation condition
-  (Definition 2.1 of Section 2.7), checked with an independently derived potential;
+  (Definition 2.1 of Section 2.8), checked with an independently derived potential;
 * entropy variables are the gradient of the entropy (complex-step), round trip;
 * scheme: lake at rest (Theorem 2.2 and Section 2.8), free stream, entropy
   conservation / dissipation, conservation of mass and momentum;
