@@ -140,7 +140,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--n", type=int, default=64, help="squares per side (64 -> 8192 triangles)")
     ap.add_argument("--N", type=int, default=3)
     ap.add_argument("--epb", type=int, default=0, help="elements per workgroup (0 = tuned default)")
@@ -197,12 +197,12 @@ def main():
     ms = results[prec]
     t_stage = ms * 1e-3 / (5 * args.steps)
     value = dof / t_stage
-    word = 4 if prec == "fp32" else 8
+    word = 8 if prec == "fp64" else 4
     flops = alg_flops_per_elem(w.N) * w.K
     byts = alg_bytes_per_elem(w.N, word) * w.K
     achieved_tf = flops / t_stage / 1e12
     achieved_gbs = byts / t_stage / 1e9
-    peak_alu = PEAK_FP32_TFLOPS if prec == "fp32" else PEAK_FP64_TFLOPS
+    peak_alu = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
     frac_alu = achieved_tf / peak_alu
     frac_hbm = achieved_gbs / PEAK_HBM_GBS
     if frac_alu >= frac_hbm:
@@ -228,7 +228,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == "fp32" else "f64",
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "f32 (bf16x3 contractions)"}[prec],
         "data": "synthetic",
         "config": {"workload": f"curved periodic lake at rest + Gaussian bump, {args.n}x{args.n}x2={w.K} triangles, "
                                f"N={w.N} (Np={Np}, Nq={Nq}, Nfq={Nfq}), LF flux, LSRK4(5)",

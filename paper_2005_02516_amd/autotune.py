@@ -47,8 +47,10 @@ def lookup(precision: str, sizes: Iterable[Tuple[int, int]]) -> Optional[Dict[in
     out = {}
     order = {"S": ("S", "M", "L"), "M": ("M", "L", "S"), "L": ("L", "M", "S")}
     for N, K in totals.items():
-        for cls in order[size_class(K)]:        # nearest tuned size class
-            e = cache.get(f"{precision}:N{N}:{cls}")
+        # nearest tuned size class; the bf16x3 mode has the float LDS footprint
+        for prec in ((precision, "fp32") if precision == "bf16x3" else (precision,)):
+            e = next((cache[f"{prec}:N{N}:{cls}"] for cls in order[size_class(K)]
+                      if f"{prec}:N{N}:{cls}" in cache), None)
             if e:
                 out[N] = int(e["epb"])
                 break

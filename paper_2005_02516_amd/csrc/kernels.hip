@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "device_types.hpp"
 
@@ -33,6 +34,58 @@ namespace esdg {
 
 __device__ inline bool bad_value(double h, double a, double b) {
   return !(h > 0.0) || !isfinite(h) || !isfinite(a) || !isfinite(b);
+}
+
+// ---------------------------------------------------------------- split-bf16 MFMA contractions
+// C[M x NC] = A[M x KD] B[KD x NC] with A and B read from LDS in float, each split as
+// x = hi + lo (hi = bf16(x), lo = bf16(x - hi)); the product is hi_a hi_b + hi_a lo_b +
+// lo_a hi_b accumulated in float by v_mfma_f32_16x16x16_bf16 (relative error ~2^-16 per
+// product: the lo_a lo_b term and the bits below lo are dropped).  One wave per 16x16
+// output block; blocks are dealt to the workgroup's waves.  Operand layout of the
+// instruction: lane l holds A[row l%16][k 4(l/16)..4(l/16)+3], B[k 4(l/16)..+3][col l%16],
+// and receives D[rows 4(l/16)..+3][col l%16].  Out-of-range rows, columns and k are zero.
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline unsigned short bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);            // round to nearest even (finite inputs)
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_value(unsigned short h) { return __uint_as_float(unsigned(h) << 16); }
+
+template <class FA, class FB, class FC>
+__device__ void gemm_bf16x3(int M, int KD, int NC, FA a_at, FB b_at, FC c_store) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int mb = (M + 15) / 16, nb = (NC + 15) / 16, kb = (KD + 15) / 16;
+  const int lrow = lane & 15, kq = (lane >> 4) * 4;
+  for (int blk = wave; blk < mb * nb; blk += nwaves) {
+    const int bi = blk % mb, bj = blk / mb;
+    const int row = bi * 16 + lrow, col = bj * 16 + lrow;
+    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+    for (int kk = 0; kk < kb; ++kk) {
+      bf16x4_t ahi, alo, bhi, blo;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = kk * 16 + kq + r;
+        const float av = (row < M && k < KD) ? a_at(row, k) : 0.f;
+        const float bv = (col < NC && k < KD) ? b_at(k, col) : 0.f;
+        const unsigned short ah = bf16_rne(av), bh = bf16_rne(bv);
+        ahi[r] = short(ah);
+        alo[r] = short(bf16_rne(av - bf16_value(ah)));
+        bhi[r] = short(bh);
+        blo[r] = short(bf16_rne(bv - bf16_value(bh)));
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = bi * 16 + kq + r;
+      if (i < M && col < NC) c_store(i, col, acc[r]);
+    }
+  }
 }
 
 // LDS carve-up of one tile (see lds_words()).
@@ -83,22 +136,39 @@ template <int N> struct ColParts { static constexpr int value = 2; };
 //   (FP64); v'_h = Minv_k V_q^T diag(w J) v'_q; v~' = V_h v'_h;
 //   H~ - Href = (v~1' + |v~23|^2/2)/g, h~ = Href + (H~ - Href) - b~ (FP64).
 // Subtracting the constant g Href is exact: the projection reproduces constants.
-template <typename real, int N>
+template <typename real, int N, bool BF>
 __device__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L, real *out, int32_t *flag) {
+  constexpr bool bf16x3 = BF;
   constexpr int Np = dim_Np(N), Nq = dim_Nq(N), Nh = dim_Nh(N);
   const int K = d.K;
   const double g = d.g, Href = d.Href;
   const int tid = threadIdx.x, nth = blockDim.x;
+  const int nc = 3 * ne;                       // contraction columns: (field, element)
+  real *Stage = L.R;                           // [3][ne][Nq] or [3][ne][Nh] staging (free here)
   bool bad = false;
+  if constexpr (BF) {
+    {                              // u_q = V_q u_h on the matrix cores
+      gemm_bf16x3(Nq, Np, nc, [&](int i, int k) { return L.Vh[i * Np + k]; },
+                  [&](int k, int c) { return L.U[c * Np + k]; },
+                  [&](int i, int c, float v) { Stage[c * Nq + i] = v; });
+      __syncthreads();
+    }
+  }
   for (int i = tid; i < ne * Nq; i += nth) {
     const int e = i / Nq, q = i - e * Nq;
     real u0 = 0, u1 = 0, u2 = 0;
+    if (bf16x3) {
+      u0 = Stage[(0 * ne + e) * Nq + q];
+      u1 = Stage[(1 * ne + e) * Nq + q];
+      u2 = Stage[(2 * ne + e) * Nq + q];
+    } else {
 #pragma unroll 4
-    for (int j = 0; j < Np; ++j) {
-      const real v = L.Vh[q * Np + j];
-      u0 += v * L.U[0 * ne * Np + e * Np + j];
-      u1 += v * L.U[1 * ne * Np + e * Np + j];
-      u2 += v * L.U[2 * ne * Np + e * Np + j];
+      for (int j = 0; j < Np; ++j) {
+        const real v = L.Vh[q * Np + j];
+        u0 += v * L.U[0 * ne * Np + e * Np + j];
+        u1 += v * L.U[1 * ne * Np + e * Np + j];
+        u2 += v * L.U[2 * ne * Np + e * Np + j];
+      }
     }
     const double eta = u0, hu = u1, hv = u2;
     const double h = eta + Href - double(L.bq[i]);
@@ -112,7 +182,12 @@ __device__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L,
   }
   __syncthreads();
   // y = V_q^T (w J v'): one task per (field, element, mode)
-  for (int i = tid; i < 3 * ne * Np; i += nth) {
+  if constexpr (BF) {
+      gemm_bf16x3(Np, Nq, nc, [&](int i, int k) { return L.Vh[k * Np + i]; },
+                  [&](int k, int c) { return L.Q[c * Nq + k]; },
+                  [&](int i, int c, float v) { L.T[c * Np + i] = v; });
+  }
+  for (int i = tid; i < 3 * ne * Np && !bf16x3; i += nth) {
     const int c = i / (ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
     const real *Qc = L.Q + c * ne * Nq + e * Nq;
     real ya = 0, yb = 0;
@@ -140,16 +215,30 @@ __device__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L,
     L.U[i] = va + vb;
   }
   __syncthreads();
+  if constexpr (BF) {
+    {                              // v~ = V_h v_h on the matrix cores
+      gemm_bf16x3(Nh, Np, nc, [&](int i, int k) { return L.Vh[i * Np + k]; },
+                  [&](int k, int c) { return L.U[c * Np + k]; },
+                  [&](int i, int c, float v) { Stage[c * Nh + i] = v; });
+      __syncthreads();
+    }
+  }
   const size_t plane = size_t(K) * Nh;
   for (int i = tid; i < ne * Nh; i += nth) {
     const int e = i / Nh, n = i - e * Nh;
     real t0 = 0, t1 = 0, t2 = 0;
+    if (bf16x3) {
+      t0 = Stage[(0 * ne + e) * Nh + n];
+      t1 = Stage[(1 * ne + e) * Nh + n];
+      t2 = Stage[(2 * ne + e) * Nh + n];
+    } else {
 #pragma unroll 4
-    for (int j = 0; j < Np; ++j) {
-      const real v = L.Vh[n * Np + j];
-      t0 += v * L.U[0 * ne * Np + e * Np + j];
-      t1 += v * L.U[1 * ne * Np + e * Np + j];
-      t2 += v * L.U[2 * ne * Np + e * Np + j];
+      for (int j = 0; j < Np; ++j) {
+        const real v = L.Vh[n * Np + j];
+        t0 += v * L.U[0 * ne * Np + e * Np + j];
+        t1 += v * L.U[1 * ne * Np + e * Np + j];
+        t2 += v * L.U[2 * ne * Np + e * Np + j];
+      }
     }
     const double v1 = t0, v2 = t1, v3 = t2;
     const double dH = (v1 + 0.5 * (v2 * v2 + v3 * v3)) / g;
@@ -332,7 +421,7 @@ __device__ void residual_tile(const InstDesc &d, int ne, Lds<real, N> &L) {
   }
 }
 
-template <typename real, int N, int R>
+template <typename real, int N, int R, bool BF>
 __device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm, real *tile) {
   constexpr int Np = dim_Np(N), Nh = dim_Nh(N);
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -341,7 +430,7 @@ __device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
   fetch_tile<real, N>(a, d, k0, ne, L);
   if (a.mode == kProject) {
     __syncthreads();
-    project_tile<real, N>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]), a.flag);
+    project_tile<real, N, BF>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]), a.flag);
     return;
   }
   __syncthreads();
@@ -365,7 +454,16 @@ __device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
   residual_tile<real, N, R, ColParts<N>::value>(d, ne, L);
   __syncthreads();
   // lift: y = V_h^T r_h (r_h = sum of the P partials), one task per (field, element, mode)
-  for (int i = tid; i < 3 * ne * Np; i += nth) {
+  constexpr bool bf16x3 = BF;
+  if constexpr (BF) {
+    {
+      constexpr int P = ColParts<N>::value;
+      gemm_bf16x3(Np, Nh, 3 * ne, [&](int i, int k) { return L.Vh[k * Np + i]; },
+                  [&](int k, int c) { return P > 1 ? L.R[c * Nh + k] + L.R[3 * ne * Nh + c * Nh + k] : L.R[c * Nh + k]; },
+                  [&](int i, int c, float v) { L.T[c * Np + i] = v; });
+    }
+  }
+  for (int i = tid; i < 3 * ne * Np && !bf16x3; i += nth) {
     const int c = i / (ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
     const real *Rc = L.R + c * ne * Nh + e * Nh;
     real ya = 0, yb = 0;
@@ -414,7 +512,7 @@ __device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
   }
   if (a.mode == kStage) {
     __syncthreads();
-    project_tile<real, N>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]), a.flag);
+    project_tile<real, N, BF>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]), a.flag);
   }
 }
 
@@ -425,7 +523,7 @@ __device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
 // (b mod kXcds) * (gridDim / kXcds) + b / kXcds: each XCD owns a contiguous run of tiles
 // and face neighbours written by the previous stage tend to sit in its L2.  The
 // reference-operator block stays in LDS and is reloaded only when the degree changes.
-template <typename real>
+template <typename real, bool BF>
 __global__ void __launch_bounds__(kBlock, 2) stage_kernel(StageArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   real *sm = reinterpret_cast<real *>(smem_raw);
@@ -446,11 +544,11 @@ __global__ void __launch_bounds__(kBlock, 2) stage_kernel(StageArgs a) {
       loaded_N = d.N;
     }
     switch (d.N) {
-      case 1: stage_tile<real, 1, RowsPerThread<1>::value>(a, d, tl.k0, tl.ne, sm, tile); break;
-      case 2: stage_tile<real, 2, RowsPerThread<2>::value>(a, d, tl.k0, tl.ne, sm, tile); break;
-      case 3: stage_tile<real, 3, RowsPerThread<3>::value>(a, d, tl.k0, tl.ne, sm, tile); break;
-      case 4: stage_tile<real, 4, RowsPerThread<4>::value>(a, d, tl.k0, tl.ne, sm, tile); break;
-      case 5: stage_tile<real, 5, RowsPerThread<5>::value>(a, d, tl.k0, tl.ne, sm, tile); break;
+      case 1: stage_tile<real, 1, RowsPerThread<1>::value, BF>(a, d, tl.k0, tl.ne, sm, tile); break;
+      case 2: stage_tile<real, 2, RowsPerThread<2>::value, BF>(a, d, tl.k0, tl.ne, sm, tile); break;
+      case 3: stage_tile<real, 3, RowsPerThread<3>::value, BF>(a, d, tl.k0, tl.ne, sm, tile); break;
+      case 4: stage_tile<real, 4, RowsPerThread<4>::value, BF>(a, d, tl.k0, tl.ne, sm, tile); break;
+      case 5: stage_tile<real, 5, RowsPerThread<5>::value, BF>(a, d, tl.k0, tl.ne, sm, tile); break;
       default: break;
     }
     __syncthreads();
@@ -520,25 +618,27 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagArgs a) {
 
 // ---------------------------------------------------------------- host launchers
 
+static const void *stage_fn(bool fp64, bool bf16x3) {
+  if (fp64) return reinterpret_cast<const void *>(&stage_kernel<double, false>);
+  if (bf16x3) return reinterpret_cast<const void *>(&stage_kernel<float, true>);
+  return reinterpret_cast<const void *>(&stage_kernel<float, false>);
+}
+
 // Workgroups of the stage kernel that stay resident on the whole device.
-hipError_t stage_max_blocks(bool fp64, size_t lds_bytes, int *out) {
+hipError_t stage_max_blocks(bool fp64, bool bf16x3, size_t lds_bytes, int *out) {
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const void *fn = fp64 ? reinterpret_cast<const void *>(&stage_kernel<double>)
-                        : reinterpret_cast<const void *>(&stage_kernel<float>);
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, lds_bytes);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_fn(fp64, bf16x3), kBlock, lds_bytes);
   if (e != hipSuccess) return e;
   *out = ncu * (per_cu > 0 ? per_cu : 1);
   return hipSuccess;
 }
 
-hipError_t set_stage_lds_limit(bool fp64, size_t lds_bytes) {
-  const void *fn = fp64 ? reinterpret_cast<const void *>(&stage_kernel<double>)
-                        : reinterpret_cast<const void *>(&stage_kernel<float>);
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
+hipError_t set_stage_lds_limit(bool fp64, bool bf16x3, size_t lds_bytes) {
+  return hipFuncSetAttribute(stage_fn(fp64, bf16x3), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
 }
 
 // Persistent grid: at most max_blocks (what stays resident), at most one block per tile,
@@ -553,9 +653,11 @@ hipError_t launch_stage(bool fp64, const StageArgs &a, int max_blocks, size_t ld
   if (a.ntiles <= 0) return hipSuccess;
   const int grid = stage_grid(a.ntiles, max_blocks);
   if (fp64)
-    hipLaunchKernelGGL(stage_kernel<double>, dim3(grid), dim3(kBlock), lds_bytes, stream, a);
+    hipLaunchKernelGGL((stage_kernel<double, false>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
+  else if (a.bf16x3)
+    hipLaunchKernelGGL((stage_kernel<float, true>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
   else
-    hipLaunchKernelGGL(stage_kernel<float>, dim3(grid), dim3(kBlock), lds_bytes, stream, a);
+    hipLaunchKernelGGL((stage_kernel<float, false>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
   return hipGetLastError();
 }
 

@@ -5,8 +5,13 @@ projection covers all elements, which the sampled rows need through their neighb
 so these run at K = 8192 (N=3), 131072 (N=4) and 524288 (N=5), and on a stratified
 subset of the ensemble (two instances per degree, smallest and largest K drawn).
 """
+import os
+import sys
+
 import numpy as np
 import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 
 from oracle import esdg_oracle as O
 from paper_2005_02516_amd import workloads as wl
@@ -148,3 +153,30 @@ def test_graph_replay_matches_direct_fp32(torch_mod):
         out.append(s.get_state(0))
         s.close()
     assert np.array_equal(out[0], out[1])
+
+
+def test_config5_full_sampled_bf16x3(torch_mod):
+    """Config 5's own mode: split-bf16 projection and lift contractions, float flux
+    differencing, double entropy round trip (eps_eff = 2^-16 in the rounding bound)."""
+    w = wl.config5()
+    s = _solver([w], "bf16x3")
+    s.set_state(0, w.u_nodes)
+    st = s.state_device(0)
+    rhs = torch_mod.empty_like(st)
+    s.rhs(0, st, rhs)
+    s.sync()
+    r_gpu = rhs.cpu().double().numpy()
+    uh = s.get_state(0)
+    s.close()
+    d = O.Discretization(w.N, w.xg, w.yg, w.b_nodes, w.g, w.Lx, w.Ly)
+    o = O.Oracle(d, w.flux)
+    (cx, cy) = w.meta["center"]
+    dx = (w.xg.mean(axis=1) - cx + 1.0) % 2.0 - 1.0
+    dy = (w.yg.mean(axis=1) - cy + 1.0) % 2.0 - 1.0
+    ks = np.union1d(np.random.default_rng(1).choice(w.K, 256, replace=False),
+                    np.nonzero(dx * dx + dy * dy < 0.15 ** 2)[0])
+    r_ref = o.rhs(uh, ks)
+    ok, worst = check_rhs(r_gpu[:, ks], r_ref, rhs_abs_bound(o, uh, ks), 2.0 ** -16)
+    print(f"config5 bf16x3: worst err / (2^-16 bound) {worst:.3f}, max err / max|rhs| "
+          f"{np.abs(r_gpu[:, ks] - r_ref).max() / np.abs(r_ref).max():.2e}", flush=True)
+    assert ok, worst

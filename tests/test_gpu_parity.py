@@ -7,8 +7,13 @@ field after 100 steps (momentum normalised by ||h|| where it starts at zero).
 """
 import math
 
+import os
+import sys
+
 import numpy as np
 import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 
 from oracle import esdg_oracle as O
 from paper_2005_02516_amd import workloads as wl
@@ -251,3 +256,45 @@ def test_error_paths(torch):
         s.step(-1.0, 1)
     assert e.value.status == ESDG_EINVAL
     s.close()
+
+
+@pytest.mark.parametrize("N,n", [(3, 4), (5, 2)])
+def test_rhs_bf16x3(torch, N, n):
+    """Split-bf16 (hi*hi + hi*lo + lo*hi, float accumulate) contractions on the matrix cores:
+    one RHS within 64 eps_eff of the rounding bound, eps_eff = 2^-16 (the split's per-product
+    relative error)."""
+    from parity_util import check_rhs, rhs_abs_bound
+    w = wl.config2(n=n, N=N)
+    d, o = oracle_for(w, "lf")
+    s = solver(w, "bf16x3", "lf")
+    s.set_state(0, w.u_nodes)
+    uh32 = s.get_state(0)
+    st = s.state_device(0)
+    rhs = torch.empty_like(st)
+    s.rhs(0, st, rhs)
+    s.sync()
+    s.close()
+    ks = np.arange(w.K)
+    r_ref = o.rhs(uh32)
+    ok, worst = check_rhs(rhs.cpu().double().numpy(), r_ref, rhs_abs_bound(o, uh32, ks), 2.0 ** -16)
+    print(f"bf16x3 N={N}: worst err / (2^-16 * bound) = {worst:.3f}", flush=True)
+    assert ok, worst
+
+
+def test_bf16x3_100_steps_small(torch):
+    """Config-2 recipe on a 16x16x2 mesh, BF16x3 contractions: state error after 100 steps,
+    reported per field (rel L2; momentum also normalised by ||h||)."""
+    w = wl.config2(n=16, N=3)
+    d, o = oracle_for(w, "lf")
+    s = solver(w, "bf16x3", "lf")
+    s.set_state(0, w.u_nodes)
+    uh0 = d.interpolate(w.u_nodes)
+    s.step(w.dt, 100)
+    u_gpu = s.get_state(0)
+    s.close()
+    u_ref, _ = O.run(o, uh0, w.dt, 100)
+    hn = np.linalg.norm(u_ref[0])
+    err_h = np.array([np.linalg.norm(u_gpu[c] - u_ref[c]) / hn for c in range(3)])
+    err = np.array([np.linalg.norm(u_gpu[c] - u_ref[c]) / np.linalg.norm(u_ref[c]) for c in range(3)])
+    print("bf16x3 100-step rel-L2 per field:", err, "normalised by ||h||:", err_h, flush=True)
+    assert np.all(err_h < 1e-5), err_h
