@@ -107,7 +107,8 @@ def ensemble(args, torch):
     res = {}
     for prec in ([args.precision] + ([] if args.no_fp64 else ["fp64"])):
         t0 = time.perf_counter()
-        s = EsdgSwe(ws, precision=prec, flux="lf", g=1.0, use_graph=not args.no_graph)
+        s = EsdgSwe(ws, precision=prec, flux="lf", g=1.0, use_graph=not args.no_graph,
+                    matrix_cores=args.matrix_cores)
         for i, w in enumerate(ws):
             s.set_state(i, w.u_nodes)
         print(f"# {prec}: planned and set in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -147,6 +148,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--matrix-cores", action="store_true",
+                    help="projection/lift contractions on the matrix cores in the bulk precision")
     ap.add_argument("--ensemble", type=int, default=0,
                     help="time the batched ensemble of this many instances instead (256 = the full ensemble)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -181,7 +184,8 @@ def main():
     states = {}
     precs = [args.precision] + ([] if args.no_fp64 or args.precision == "fp64" else ["fp64"])
     for prec in precs:
-        s = EsdgSwe([w], precision=prec, flux=w.flux, g=w.g, elems_per_block=args.epb, use_graph=not args.no_graph)
+        s = EsdgSwe([w], precision=prec, flux=w.flux, g=w.g, elems_per_block=args.epb, use_graph=not args.no_graph,
+                    matrix_cores=args.matrix_cores)
         s.set_state(0, w.u_nodes)
         s.step(w.dt, args.warmup)
         s.sync()
@@ -232,7 +236,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"curved periodic lake at rest + Gaussian bump, {args.n}x{args.n}x2={w.K} triangles, "
                                f"N={w.N} (Np={Np}, Nq={Nq}, Nfq={Nfq}), LF flux, LSRK4(5)",
-                   "K": w.K, "N": w.N, "DOF": dof, "precision": prec, "hip_graph": not args.no_graph},
+                   "K": w.K, "N": w.N, "DOF": dof, "precision": prec, "hip_graph": not args.no_graph,
+                   "matrix_cores": bool(args.matrix_cores or prec == "bf16x3")},
         "roofline": roof,
     }
     if "fp64" in results and prec != "fp64":

@@ -102,6 +102,9 @@ typedef struct {
   int32_t use_graph;        /* nonzero: esdg_swe_step replays HIP graphs of its RK stages    */
   int32_t elems_per_block[6]; /* elements per workgroup for degree N = index (1..5); 0 = the
                                  library's default for that degree; index 0 unused            */
+  int32_t matrix_cores;     /* projection/lift contractions with constant operators: 0 or 1 =
+                               vector ALUs, 2 = matrix cores (MFMA) in the bulk precision;
+                               ESDG_FP32_BF16X3 always uses the split-bf16 matrix-core path  */
 } esdg_swe_options;
 
 /* Plan a solver for n_inst independent instances (n_inst = 1 for a single run).  Builds,

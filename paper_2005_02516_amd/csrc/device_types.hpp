@@ -77,7 +77,8 @@ struct StageArgs {
   int32_t ntiles;
   int32_t mode;
   int32_t ref_words_max;  // LDS words reserved for the reference block (largest degree)
-  int32_t bf16x3;         // nonzero: constant-matrix contractions as split-bf16 MFMA products
+  int32_t contraction;    // constant-matrix contractions: 0 VALU, 1 matrix cores in the bulk
+                          // precision, 2 matrix cores with split-bf16 products
   const int32_t *ranges;  // optional [grid+1]: tile range of each block's chunk (cost-balanced);
                           // null means equal numbers of tiles per chunk
   int32_t in_buf, out_buf;

@@ -36,16 +36,22 @@ __device__ inline bool bad_value(double h, double a, double b) {
   return !(h > 0.0) || !isfinite(h) || !isfinite(a) || !isfinite(b);
 }
 
-// ---------------------------------------------------------------- split-bf16 MFMA contractions
-// C[M x NC] = A[M x KD] B[KD x NC] with A and B read from LDS in float, each split as
-// x = hi + lo (hi = bf16(x), lo = bf16(x - hi)); the product is hi_a hi_b + hi_a lo_b +
-// lo_a hi_b accumulated in float by v_mfma_f32_16x16x16_bf16 (relative error ~2^-16 per
-// product: the lo_a lo_b term and the bits below lo are dropped).  One wave per 16x16
-// output block; blocks are dealt to the workgroup's waves.  Operand layout of the
-// instruction: lane l holds A[row l%16][k 4(l/16)..4(l/16)+3], B[k 4(l/16)..+3][col l%16],
-// and receives D[rows 4(l/16)..+3][col l%16].  Out-of-range rows, columns and k are zero.
+// ---------------------------------------------------------------- matrix-core contractions
+// C[M x NC] = A[M x KD] B[KD x NC], A and B read from LDS, on the matrix cores.  One wave
+// per 16x16 output block; blocks are dealt to the workgroup's waves.  Lane layout of the
+// 16x16xK instructions used: lane l holds A[row l%16][k in k-quad l/16], B[k in k-quad
+// l/16][col l%16] and receives D[rows 4(l/16)..4(l/16)+3][col l%16].  Out-of-range rows,
+// columns and k are zero.  Modes:
+//   kMfmaNative: v_mfma_f32_16x16x4_f32 or v_mfma_f64_16x16x4_f64 (same rounding as the
+//                VALU path up to summation order);
+//   kMfmaBf16x3: each operand split x = hi + lo (hi = bf16(x), lo = bf16(x - hi)), product
+//                hi_a hi_b + hi_a lo_b + lo_a hi_b by v_mfma_f32_16x16x16_bf16 with float
+//                accumulation (relative error ~2^-16 per product).
+enum ContractionMode : int { kValu = 0, kMfmaNative = 1, kMfmaBf16x3 = 2 };
+
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
 
 __device__ inline unsigned short bf16_rne(float x) {
   unsigned u = __float_as_uint(x);
@@ -54,36 +60,68 @@ __device__ inline unsigned short bf16_rne(float x) {
 }
 __device__ inline float bf16_value(unsigned short h) { return __uint_as_float(unsigned(h) << 16); }
 
-template <class FA, class FB, class FC>
-__device__ void gemm_bf16x3(int M, int KD, int NC, FA a_at, FB b_at, FC c_store) {
+template <int MODE, typename real, class FA, class FB, class FC>
+__device__ __forceinline__ void gemm_mfma(int M, int KD, int NC, FA a_at, FB b_at, FC c_store) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  const int mb = (M + 15) / 16, nb = (NC + 15) / 16, kb = (KD + 15) / 16;
-  const int lrow = lane & 15, kq = (lane >> 4) * 4;
+  const int mb = (M + 15) / 16, nb = (NC + 15) / 16;
+  const int lrow = lane & 15, quad = lane >> 4;
+#pragma unroll 1
   for (int blk = wave; blk < mb * nb; blk += nwaves) {
     const int bi = blk % mb, bj = blk / mb;
     const int row = bi * 16 + lrow, col = bj * 16 + lrow;
-    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-    for (int kk = 0; kk < kb; ++kk) {
-      bf16x4_t ahi, alo, bhi, blo;
+    if constexpr (MODE == kMfmaBf16x3) {
+      f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+      for (int k0 = 0; k0 < KD; k0 += 16) {
+        bf16x4_t ahi, alo, bhi, blo;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = k0 + 4 * quad + r;
+          const float av = (row < M && k < KD) ? float(a_at(row, k)) : 0.f;
+          const float bv = (col < NC && k < KD) ? float(b_at(k, col)) : 0.f;
+          const unsigned short ah = bf16_rne(av), bh = bf16_rne(bv);
+          ahi[r] = short(ah);
+          alo[r] = short(bf16_rne(av - bf16_value(ah)));
+          bhi[r] = short(bh);
+          blo[r] = short(bf16_rne(bv - bf16_value(bh)));
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc, 0, 0, 0);
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int k = kk * 16 + kq + r;
+        const int i = bi * 16 + 4 * quad + r;
+        if (i < M && col < NC) c_store(i, col, real(acc[r]));
+      }
+    } else if constexpr (std::is_same<real, float>::value) {
+      f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+      for (int k0 = 0; k0 < KD; k0 += 4) {
+        const int k = k0 + quad;
         const float av = (row < M && k < KD) ? a_at(row, k) : 0.f;
         const float bv = (col < NC && k < KD) ? b_at(k, col) : 0.f;
-        const unsigned short ah = bf16_rne(av), bh = bf16_rne(bv);
-        ahi[r] = short(ah);
-        alo[r] = short(bf16_rne(av - bf16_value(ah)));
-        bhi[r] = short(bh);
-        blo[r] = short(bf16_rne(bv - bf16_value(bh)));
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
       }
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc, 0, 0, 0);
-    }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = bi * 16 + kq + r;
-      if (i < M && col < NC) c_store(i, col, acc[r]);
+      for (int r = 0; r < 4; ++r) {
+        const int i = bi * 16 + 4 * quad + r;
+        if (i < M && col < NC) c_store(i, col, acc[r]);
+      }
+    } else {
+      f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+      for (int k0 = 0; k0 < KD; k0 += 4) {
+        const int k = k0 + quad;
+        const double av = (row < M && k < KD) ? a_at(row, k) : 0.0;
+        const double bv = (col < NC && k < KD) ? b_at(k, col) : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = bi * 16 + 4 * quad + r;
+        if (i < M && col < NC) c_store(i, col, acc[r]);
+      }
     }
   }
 }
@@ -136,9 +174,9 @@ template <int N> struct ColParts { static constexpr int value = 2; };
 //   (FP64); v'_h = Minv_k V_q^T diag(w J) v'_q; v~' = V_h v'_h;
 //   H~ - Href = (v~1' + |v~23|^2/2)/g, h~ = Href + (H~ - Href) - b~ (FP64).
 // Subtracting the constant g Href is exact: the projection reproduces constants.
-template <typename real, int N, bool BF>
-__device__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L, real *out, int32_t *flag) {
-  constexpr bool bf16x3 = BF;
+template <typename real, int N, int CM>
+__device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L, real *out, int32_t *flag) {
+  constexpr bool mfma = CM != kValu;
   constexpr int Np = dim_Np(N), Nq = dim_Nq(N), Nh = dim_Nh(N);
   const int K = d.K;
   const double g = d.g, Href = d.Href;
@@ -146,18 +184,18 @@ __device__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L,
   const int nc = 3 * ne;                       // contraction columns: (field, element)
   real *Stage = L.R;                           // [3][ne][Nq] or [3][ne][Nh] staging (free here)
   bool bad = false;
-  if constexpr (BF) {
+  if constexpr (CM != kValu) {
     {                              // u_q = V_q u_h on the matrix cores
-      gemm_bf16x3(Nq, Np, nc, [&](int i, int k) { return L.Vh[i * Np + k]; },
+      gemm_mfma<CM, real>(Nq, Np, nc, [&](int i, int k) { return L.Vh[i * Np + k]; },
                   [&](int k, int c) { return L.U[c * Np + k]; },
-                  [&](int i, int c, float v) { Stage[c * Nq + i] = v; });
+                  [&](int i, int c, real v) { Stage[c * Nq + i] = v; });
       __syncthreads();
     }
   }
   for (int i = tid; i < ne * Nq; i += nth) {
     const int e = i / Nq, q = i - e * Nq;
     real u0 = 0, u1 = 0, u2 = 0;
-    if (bf16x3) {
+    if (mfma) {
       u0 = Stage[(0 * ne + e) * Nq + q];
       u1 = Stage[(1 * ne + e) * Nq + q];
       u2 = Stage[(2 * ne + e) * Nq + q];
@@ -182,12 +220,12 @@ __device__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L,
   }
   __syncthreads();
   // y = V_q^T (w J v'): one task per (field, element, mode)
-  if constexpr (BF) {
-      gemm_bf16x3(Np, Nq, nc, [&](int i, int k) { return L.Vh[k * Np + i]; },
+  if constexpr (CM != kValu) {
+      gemm_mfma<CM, real>(Np, Nq, nc, [&](int i, int k) { return L.Vh[k * Np + i]; },
                   [&](int k, int c) { return L.Q[c * Nq + k]; },
-                  [&](int i, int c, float v) { L.T[c * Np + i] = v; });
+                  [&](int i, int c, real v) { L.T[c * Np + i] = v; });
   }
-  for (int i = tid; i < 3 * ne * Np && !bf16x3; i += nth) {
+  for (int i = tid; i < 3 * ne * Np && !mfma; i += nth) {
     const int c = i / (ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
     const real *Qc = L.Q + c * ne * Nq + e * Nq;
     real ya = 0, yb = 0;
@@ -215,11 +253,11 @@ __device__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L,
     L.U[i] = va + vb;
   }
   __syncthreads();
-  if constexpr (BF) {
+  if constexpr (CM != kValu) {
     {                              // v~ = V_h v_h on the matrix cores
-      gemm_bf16x3(Nh, Np, nc, [&](int i, int k) { return L.Vh[i * Np + k]; },
+      gemm_mfma<CM, real>(Nh, Np, nc, [&](int i, int k) { return L.Vh[i * Np + k]; },
                   [&](int k, int c) { return L.U[c * Np + k]; },
-                  [&](int i, int c, float v) { Stage[c * Nh + i] = v; });
+                  [&](int i, int c, real v) { Stage[c * Nh + i] = v; });
       __syncthreads();
     }
   }
@@ -227,7 +265,7 @@ __device__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L,
   for (int i = tid; i < ne * Nh; i += nth) {
     const int e = i / Nh, n = i - e * Nh;
     real t0 = 0, t1 = 0, t2 = 0;
-    if (bf16x3) {
+    if (mfma) {
       t0 = Stage[(0 * ne + e) * Nh + n];
       t1 = Stage[(1 * ne + e) * Nh + n];
       t2 = Stage[(2 * ne + e) * Nh + n];
@@ -270,7 +308,7 @@ __device__ inline void async_copy_words(uint32_t *dst, const uint32_t *src, int 
 
 // Phase 0: fetch the tile's global data into LDS (all asynchronous; see above).
 template <typename real, int N>
-__device__ void fetch_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, Lds<real, N> &L) {
+__device__ __forceinline__ void fetch_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, Lds<real, N> &L) {
   constexpr int Np = dim_Np(N), Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
   constexpr int W = sizeof(real) / 4;     // 32-bit words per value
   const size_t plane = size_t(d.K) * Nh, splane = size_t(d.K) * Np;
@@ -321,7 +359,7 @@ __device__ void fetch_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
 }
 
 template <typename real, int N, int R, int P, bool FACE>
-__device__ inline void row_block(const InstDesc &d, int ne, int e, int b, int p, Lds<real, N> &L) {
+__device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int b, int p, Lds<real, N> &L) {
   constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
   // volume rows: all Nh columns (the diagonal of the skew operator is zero);
   // face rows: the Nq volume columns (the surface-surface block is zero)
@@ -403,7 +441,7 @@ __device__ inline void row_block(const InstDesc &d, int ne, int e, int b, int p,
 // the P partial sums are added in the lift.  One flat task list: first every volume
 // task, then every face task, so whole waves take the same branch.
 template <typename real, int N, int R, int P>
-__device__ void residual_tile(const InstDesc &d, int ne, Lds<real, N> &L) {
+__device__ __forceinline__ void residual_tile(const InstDesc &d, int ne, Lds<real, N> &L) {
   constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N);
   constexpr int VB = Nq / R, FB = Nfq / R;
   static_assert(Nq % R == 0 && Nfq % R == 0, "R must divide Nq and Nfq");
@@ -421,8 +459,8 @@ __device__ void residual_tile(const InstDesc &d, int ne, Lds<real, N> &L) {
   }
 }
 
-template <typename real, int N, int R, bool BF>
-__device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm, real *tile) {
+template <typename real, int N, int R, int CM>
+__device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm, real *tile) {
   constexpr int Np = dim_Np(N), Nh = dim_Nh(N);
   const int tid = threadIdx.x, nth = blockDim.x;
   Lds<real, N> L(sm, tile, ne);
@@ -430,7 +468,7 @@ __device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
   fetch_tile<real, N>(a, d, k0, ne, L);
   if (a.mode == kProject) {
     __syncthreads();
-    project_tile<real, N, BF>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]), a.flag);
+    project_tile<real, N, CM>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]), a.flag);
     return;
   }
   __syncthreads();
@@ -454,16 +492,16 @@ __device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
   residual_tile<real, N, R, ColParts<N>::value>(d, ne, L);
   __syncthreads();
   // lift: y = V_h^T r_h (r_h = sum of the P partials), one task per (field, element, mode)
-  constexpr bool bf16x3 = BF;
-  if constexpr (BF) {
+  constexpr bool mfma = CM != kValu;
+  if constexpr (CM != kValu) {
     {
       constexpr int P = ColParts<N>::value;
-      gemm_bf16x3(Np, Nh, 3 * ne, [&](int i, int k) { return L.Vh[k * Np + i]; },
+      gemm_mfma<CM, real>(Np, Nh, 3 * ne, [&](int i, int k) { return L.Vh[k * Np + i]; },
                   [&](int k, int c) { return P > 1 ? L.R[c * Nh + k] + L.R[3 * ne * Nh + c * Nh + k] : L.R[c * Nh + k]; },
-                  [&](int i, int c, float v) { L.T[c * Np + i] = v; });
+                  [&](int i, int c, real v) { L.T[c * Np + i] = v; });
     }
   }
-  for (int i = tid; i < 3 * ne * Np && !bf16x3; i += nth) {
+  for (int i = tid; i < 3 * ne * Np && !mfma; i += nth) {
     const int c = i / (ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
     const real *Rc = L.R + c * ne * Nh + e * Nh;
     real ya = 0, yb = 0;
@@ -512,7 +550,7 @@ __device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
   }
   if (a.mode == kStage) {
     __syncthreads();
-    project_tile<real, N, BF>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]), a.flag);
+    project_tile<real, N, CM>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]), a.flag);
   }
 }
 
@@ -523,7 +561,7 @@ __device__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne
 // (b mod kXcds) * (gridDim / kXcds) + b / kXcds: each XCD owns a contiguous run of tiles
 // and face neighbours written by the previous stage tend to sit in its L2.  The
 // reference-operator block stays in LDS and is reloaded only when the degree changes.
-template <typename real, bool BF>
+template <typename real, int CM>
 __global__ void __launch_bounds__(kBlock, 2) stage_kernel(StageArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   real *sm = reinterpret_cast<real *>(smem_raw);
@@ -544,11 +582,11 @@ __global__ void __launch_bounds__(kBlock, 2) stage_kernel(StageArgs a) {
       loaded_N = d.N;
     }
     switch (d.N) {
-      case 1: stage_tile<real, 1, RowsPerThread<1>::value, BF>(a, d, tl.k0, tl.ne, sm, tile); break;
-      case 2: stage_tile<real, 2, RowsPerThread<2>::value, BF>(a, d, tl.k0, tl.ne, sm, tile); break;
-      case 3: stage_tile<real, 3, RowsPerThread<3>::value, BF>(a, d, tl.k0, tl.ne, sm, tile); break;
-      case 4: stage_tile<real, 4, RowsPerThread<4>::value, BF>(a, d, tl.k0, tl.ne, sm, tile); break;
-      case 5: stage_tile<real, 5, RowsPerThread<5>::value, BF>(a, d, tl.k0, tl.ne, sm, tile); break;
+      case 1: stage_tile<real, 1, RowsPerThread<1>::value, CM>(a, d, tl.k0, tl.ne, sm, tile); break;
+      case 2: stage_tile<real, 2, RowsPerThread<2>::value, CM>(a, d, tl.k0, tl.ne, sm, tile); break;
+      case 3: stage_tile<real, 3, RowsPerThread<3>::value, CM>(a, d, tl.k0, tl.ne, sm, tile); break;
+      case 4: stage_tile<real, 4, RowsPerThread<4>::value, CM>(a, d, tl.k0, tl.ne, sm, tile); break;
+      case 5: stage_tile<real, 5, RowsPerThread<5>::value, CM>(a, d, tl.k0, tl.ne, sm, tile); break;
       default: break;
     }
     __syncthreads();
@@ -618,27 +656,30 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagArgs a) {
 
 // ---------------------------------------------------------------- host launchers
 
-static const void *stage_fn(bool fp64, bool bf16x3) {
-  if (fp64) return reinterpret_cast<const void *>(&stage_kernel<double, false>);
-  if (bf16x3) return reinterpret_cast<const void *>(&stage_kernel<float, true>);
-  return reinterpret_cast<const void *>(&stage_kernel<float, false>);
+static const void *stage_fn(bool fp64, int cm) {
+  if (fp64)
+    return cm == kMfmaNative ? reinterpret_cast<const void *>(&stage_kernel<double, kMfmaNative>)
+                             : reinterpret_cast<const void *>(&stage_kernel<double, kValu>);
+  if (cm == kMfmaBf16x3) return reinterpret_cast<const void *>(&stage_kernel<float, kMfmaBf16x3>);
+  if (cm == kMfmaNative) return reinterpret_cast<const void *>(&stage_kernel<float, kMfmaNative>);
+  return reinterpret_cast<const void *>(&stage_kernel<float, kValu>);
 }
 
 // Workgroups of the stage kernel that stay resident on the whole device.
-hipError_t stage_max_blocks(bool fp64, bool bf16x3, size_t lds_bytes, int *out) {
+hipError_t stage_max_blocks(bool fp64, int cm, size_t lds_bytes, int *out) {
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_fn(fp64, bf16x3), kBlock, lds_bytes);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_fn(fp64, cm), kBlock, lds_bytes);
   if (e != hipSuccess) return e;
   *out = ncu * (per_cu > 0 ? per_cu : 1);
   return hipSuccess;
 }
 
-hipError_t set_stage_lds_limit(bool fp64, bool bf16x3, size_t lds_bytes) {
-  return hipFuncSetAttribute(stage_fn(fp64, bf16x3), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
+hipError_t set_stage_lds_limit(bool fp64, int cm, size_t lds_bytes) {
+  return hipFuncSetAttribute(stage_fn(fp64, cm), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
 }
 
 // Persistent grid: at most max_blocks (what stays resident), at most one block per tile,
@@ -652,12 +693,17 @@ int stage_grid(int ntiles, int max_blocks) {
 hipError_t launch_stage(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream) {
   if (a.ntiles <= 0) return hipSuccess;
   const int grid = stage_grid(a.ntiles, max_blocks);
-  if (fp64)
-    hipLaunchKernelGGL((stage_kernel<double, false>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
-  else if (a.bf16x3)
-    hipLaunchKernelGGL((stage_kernel<float, true>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
+  const int cm = a.contraction;
+  if (fp64 && cm == kMfmaNative)
+    hipLaunchKernelGGL((stage_kernel<double, kMfmaNative>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
+  else if (fp64)
+    hipLaunchKernelGGL((stage_kernel<double, kValu>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
+  else if (cm == kMfmaBf16x3)
+    hipLaunchKernelGGL((stage_kernel<float, kMfmaBf16x3>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
+  else if (cm == kMfmaNative)
+    hipLaunchKernelGGL((stage_kernel<float, kMfmaNative>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
   else
-    hipLaunchKernelGGL((stage_kernel<float, false>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
+    hipLaunchKernelGGL((stage_kernel<float, kValu>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
   return hipGetLastError();
 }
 

@@ -18,9 +18,9 @@
 #include "host_setup.hpp"
 
 namespace esdg {
-hipError_t set_stage_lds_limit(bool fp64, bool bf16x3, size_t lds_bytes);
+hipError_t set_stage_lds_limit(bool fp64, int cm, size_t lds_bytes);
 hipError_t launch_stage(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream);
-hipError_t stage_max_blocks(bool fp64, bool bf16x3, size_t lds_bytes, int *out);
+hipError_t stage_max_blocks(bool fp64, int cm, size_t lds_bytes, int *out);
 int stage_grid(int ntiles, int max_blocks);
 hipError_t launch_diag(bool fp64, const DiagArgs &a, hipStream_t stream);
 }  // namespace esdg
@@ -63,6 +63,7 @@ struct esdg_swe {
   esdg_swe_options opt{};
   bool fp64 = true;
   bool bf16x3 = false;
+  int contraction = 0;             // 0 VALU, 1 matrix cores (bulk precision), 2 split-bf16
   size_t word = 8;
   std::map<int, RefElem> refs;
   std::vector<InstanceHost> host;
@@ -161,7 +162,7 @@ StageArgs base_args(esdg_swe *s, int inst) {
   }
   a.flag = s->dev<int32_t>(s->flag_off);
   a.ref_words_max = s->ref_max;
-  a.bf16x3 = s->bf16x3 ? 1 : 0;
+  a.contraction = s->contraction;
   return a;
 }
 
@@ -231,7 +232,7 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
   }
   *out = nullptr;
   if (opt->precision < ESDG_FP64 || opt->precision > ESDG_FP32_BF16X3 || opt->flux < 0 || opt->flux > 1 ||
-      !(opt->g > 0.0)) {
+      !(opt->g > 0.0) || opt->matrix_cores < 0 || opt->matrix_cores > 2) {
     g_init_error = "esdg_swe_init: option out of range";
     return ESDG_EINVAL;
   }
@@ -245,6 +246,7 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
   s->opt = *opt;
   s->fp64 = opt->precision == ESDG_FP64;
   s->bf16x3 = opt->precision == ESDG_FP32_BF16X3;
+  s->contraction = s->bf16x3 ? 2 : (opt->matrix_cores == 2 ? 1 : 0);
   s->word = s->fp64 ? 8 : 4;
   s->host.resize(n_inst);
   for (int i = 0; i < n_inst; ++i) {
@@ -339,15 +341,16 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
   s->ws = static_cast<unsigned char *>(dev_workspace);
   s->stream = static_cast<hipStream_t>(hip_stream);
   if (s->lds_bytes > 64 * 1024) {
-    hipError_t e = set_stage_lds_limit(s->fp64, s->bf16x3, s->lds_bytes);
+    hipError_t e = set_stage_lds_limit(s->fp64, s->contraction, s->lds_bytes);
     if (e != hipSuccess) return s->hip_fail(e, "hipFuncSetAttribute (LDS)");
   }
   {
-    hipError_t e = stage_max_blocks(s->fp64, s->bf16x3, s->lds_bytes, &s->max_blocks);
+    hipError_t e = stage_max_blocks(s->fp64, s->contraction, s->lds_bytes, &s->max_blocks);
     if (e != hipSuccess) return s->hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (std::getenv("ESDG_SWE_VERBOSE")) {
       std::fprintf(stderr, "esdg_swe: %s, LDS %zu B per workgroup, %d resident workgroups, %zu tiles;",
-                   s->fp64 ? "fp64" : (s->bf16x3 ? "fp32+bf16x3" : "fp32"), s->lds_bytes, s->max_blocks, s->tiles.size());
+                   s->fp64 ? (s->contraction ? "fp64+mfma" : "fp64")
+                           : (s->bf16x3 ? "fp32+bf16x3" : (s->contraction ? "fp32+mfma" : "fp32")), s->lds_bytes, s->max_blocks, s->tiles.size());
       for (auto &kv : s->epb) std::fprintf(stderr, " N=%d: %d elements/tile", kv.first, kv.second);
       std::fprintf(stderr, "\n");
     }

@@ -298,3 +298,41 @@ def test_bf16x3_100_steps_small(torch):
     err = np.array([np.linalg.norm(u_gpu[c] - u_ref[c]) / np.linalg.norm(u_ref[c]) for c in range(3)])
     print("bf16x3 100-step rel-L2 per field:", err, "normalised by ||h||:", err_h, flush=True)
     assert np.all(err_h < 1e-5), err_h
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_rhs_matrix_cores(torch, name, make, precision):
+    """Projection and lift contractions on the matrix cores in the bulk precision
+    (v_mfma_f64_16x16x4_f64 / v_mfma_f32_16x16x4_f32): one RHS within 64 eps of the
+    rounding bound, the same bar as a reordered sum in that precision."""
+    from parity_util import EPS32, EPS64, check_rhs, rhs_abs_bound
+    w = make()
+    d, o = oracle_for(w, "lf")
+    s = solver(w, precision, "lf", matrix_cores=True)
+    s.set_state(0, w.u_nodes)
+    uh = s.get_state(0)
+    st = s.state_device(0)
+    rhs = torch.empty_like(st)
+    s.rhs(0, st, rhs)
+    s.sync()
+    s.close()
+    ok, worst = check_rhs(rhs.cpu().double().numpy(), o.rhs(uh), rhs_abs_bound(o, uh, np.arange(w.K)),
+                          EPS64 if precision == "fp64" else EPS32)
+    print(f"matrix cores {precision} {name}: worst err / (eps * bound) = {worst:.3f}", flush=True)
+    assert ok, worst
+
+
+def test_steps_fp64_matrix_cores(torch):
+    """10 LSRK steps in FP64 with matrix-core contractions match the oracle to 1e-12."""
+    w = wl.config2(n=4, N=3)
+    d, o = oracle_for(w, "lf")
+    s = solver(w, "fp64", "lf", matrix_cores=True)
+    s.set_state(0, w.u_nodes)
+    uh0 = s.get_state(0)
+    s.step(w.dt, 10)
+    u = s.get_state(0)
+    s.close()
+    u_ref, _ = O.run(o, uh0, w.dt, 10)
+    err = rel_l2(u, u_ref, norm_by=np.linalg.norm(u_ref[0]))
+    assert np.all(err < 1e-12), err
