@@ -80,8 +80,8 @@ def time_config(w, precision: str, epb: int, steps: int = 4, warmup: int = 1) ->
 def lds_ok(N: int, E: int, precision: str) -> bool:
     Np, Nq, Nfq = (N + 1) * (N + 2) // 2, (N + 1) ** 2, 3 * (N + 1)
     Nh = Nq + Nfq
-    ref = Nh * Np + 2 * Nh * Nq + 2 * Nq * Nfq + 3 * Nfq
-    tile = E * (Nh * 11 + 8 * Nh + 4 * Nfq + 6 * Np + Np * Np + 2 * Nq + Nh)
+    ref = (Nh * Np + 2 * Nh * Nq + 2 * Nq * Nfq + 3 * Nfq + 3) // 4 * 4
+    tile = E * (Nh * 12 + 8 * Nh + 4 * Nfq + 6 * Np + Np * Np + 2 * Nq + Nh + Nfq)
     word = 8 if precision == "fp64" else 4
     return (ref + tile) * word <= 160 * 1024 and E * Nh <= 2048
 

@@ -8,7 +8,8 @@ namespace esdg {
 
 constexpr int kMaxN = 5;
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64s)
-constexpr int kNodeRec = 11;       // per hybrid node in LDS: hu/2 hv/2 u/2 v/2 gh/2 dH rxJ sxJ ryJ syJ h
+constexpr int kNodeRec = 12;       // per hybrid node in LDS: hu/2 hv/2 u/2 v/2 | rxJ sxJ ryJ syJ | gh/2 dH h -
+                                   // (three aligned quads, so a column is read with two 16-byte loads)
 constexpr int kXcds = 8;           // MI355X accelerator complex dies (each with its own L2)
 
 __host__ __device__ constexpr int dim_Np(int N) { return (N + 1) * (N + 2) / 2; }
@@ -37,10 +38,11 @@ __host__ __device__ constexpr int ref_words(int N) {
 // Words (of the bulk precision) of LDS one tile of E elements of degree N needs (the
 // reference block is held separately, once per workgroup): node records [E][Nh][kNodeRec] | fetched u~ and metrics [8][E][Nh] |
 // neighbour values [E][Nfq][4] | state, RK register [3][E][Np] each | Minv [E][Np][Np] |
-// w J [E][Nq] | b at volume nodes [E][Nq] | b at hybrid nodes [E][Nh].
+// w J [E][Nq] | b at volume nodes [E][Nq] | b at hybrid nodes [E][Nh] | push targets
+// [E][Nfq] (int32, one word of the bulk precision each).
 __host__ __device__ constexpr int tile_words(int N, int E) {
   return E * (dim_Nh(N) * kNodeRec + 8 * dim_Nh(N) + 4 * dim_Nfq(N) + 6 * dim_Np(N) +
-                             dim_Np(N) * dim_Np(N) + 2 * dim_Nq(N) + dim_Nh(N));
+                             dim_Np(N) * dim_Np(N) + 2 * dim_Nq(N) + dim_Nh(N) + dim_Nfq(N));
 }
 
 // One instance as the kernels see it (device pointers into the bound workspace).
@@ -50,12 +52,14 @@ struct InstDesc {
   void *uh;            // [3][K][Np] modal state (eta = h + b - Href, hu, hv)
   void *du;            // [3][K][Np] LSRK register
   void *ut[3];         // [4][K][Nh] entropy-projected h~, u~, v~, H~ - Href (two stage buffers + rhs scratch)
+  void *nbx[3];        // [K][Nfq][4] the same four values at each face node's neighbour, written
+                       // by the neighbour's projection (one per ut buffer)
   const void *geo;     // [4][K][Nh] rxJ, sxJ, ryJ, syJ
   const void *wJq;     // [K][Nq] w_q J
   const void *Minv;    // [K][Np][Np]
   const void *bq;      // [K][Nq] bathymetry at volume nodes
   const void *bh;      // [K][Nh] bathymetry at hybrid nodes
-  const int32_t *mapP; // [K][Nfq] index k'*Nh + Nq + f' of the neighbour node
+  const int32_t *pushP; // [K][Nfq] slot k'*Nfq + f' of nbx that face node f of element k fills
   const void *ref;     // reference-operator block for this N
   void *rhs_scratch;   // [3][K][Np] used by the diagnostics
 };

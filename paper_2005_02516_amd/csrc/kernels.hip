@@ -40,8 +40,9 @@ __device__ inline bool bad_value(double h, double a, double b) {
 // C[M x NC] = A[M x KD] B[KD x NC], A and B read from LDS, on the matrix cores.  One wave
 // per 16x16 output block; blocks are dealt to the workgroup's waves.  Lane layout of the
 // 16x16xK instructions used: lane l holds A[row l%16][k in k-quad l/16], B[k in k-quad
-// l/16][col l%16] and receives D[rows 4(l/16)..4(l/16)+3][col l%16].  Out-of-range rows,
-// columns and k are zero.  Modes:
+// l/16][col l%16]; it receives D[row 4(l/16) + r][col l%16], r = 0..3, from the f32 and
+// bf16 instructions, but D[row l/16 + 4r][col l%16] from v_mfma_f64_16x16x4_f64.
+// Out-of-range rows, columns and k are zero.  Modes:
 //   kMfmaNative: v_mfma_f32_16x16x4_f32 or v_mfma_f64_16x16x4_f64 (same rounding as the
 //                VALU path up to summation order);
 //   kMfmaBf16x3: each operand split x = hi + lo (hi = bf16(x), lo = bf16(x - hi)), product
@@ -119,7 +120,7 @@ __device__ __forceinline__ void gemm_mfma(int M, int KD, int NC, FA a_at, FB b_a
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = bi * 16 + 4 * quad + r;
+        const int i = bi * 16 + quad + 4 * r;      // f64 output rows are interleaved
         if (i < M && col < NC) c_store(i, col, acc[r]);
       }
     }
@@ -133,6 +134,7 @@ struct Lds {
   real *ref, *Vh, *ST, *FT, *wf, *nr, *ns;
   real *rec, *raw, *nb, *U, *DU, *Minv, *wJ, *bq, *bh;
   real *R, *T, *Q;
+  int32_t *pp;
   // sm: the ref block (already loaded); tile: the tile region (after the largest ref block)
   __device__ Lds(real *sm, real *tile, int E) {
     ref = sm;
@@ -151,6 +153,7 @@ struct Lds {
     wJ = Minv + E * Np * Np;
     bq = wJ + E * Nq;
     bh = bq + E * Nq;
+    pp = reinterpret_cast<int32_t *>(bh + E * Nh);
     // reuse: residual and lift temporaries live in the raw block (dead after phase 1),
     // the projection's pointwise values in the record block (dead after phase 2)
     R = raw;                      // up to two partial residuals [2][3][E][Nh]
@@ -163,7 +166,7 @@ struct Lds {
 template <int N> struct RowsPerThread { static constexpr int value = 1; };
 template <> struct RowsPerThread<1> { static constexpr int value = 2; };
 template <> struct RowsPerThread<3> { static constexpr int value = 2; };
-template <> struct RowsPerThread<5> { static constexpr int value = 3; };
+template <> struct RowsPerThread<5> { static constexpr int value = 1; };
 
 // Column parts of the residual phase, per degree (1 or 2).
 template <int N> struct ColParts { static constexpr int value = 2; };
@@ -175,9 +178,10 @@ template <int N> struct ColParts { static constexpr int value = 2; };
 //   H~ - Href = (v~1' + |v~23|^2/2)/g, h~ = Href + (H~ - Href) - b~ (FP64).
 // Subtracting the constant g Href is exact: the projection reproduces constants.
 template <typename real, int N, int CM>
-__device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L, real *out, int32_t *flag) {
+__device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L, real *out,
+                                             real *nbx_out, int32_t *flag) {
   constexpr bool mfma = CM != kValu;
-  constexpr int Np = dim_Np(N), Nq = dim_Nq(N), Nh = dim_Nh(N);
+  constexpr int Np = dim_Np(N), Nq = dim_Nq(N), Nh = dim_Nh(N), Nfq = dim_Nfq(N);
   const int K = d.K;
   const double g = d.g, Href = d.Href;
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -286,6 +290,11 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
     out[1 * plane + o] = real(v2);
     out[2 * plane + o] = real(v3);
     out[3 * plane + o] = real(dH);
+    if (n >= Nq) {                 // face node: also fill the neighbour's face slot
+      typedef real real4 __attribute__((ext_vector_type(4)));
+      const real4 val = {real(h), real(v2), real(v3), real(dH)};
+      *reinterpret_cast<real4 *>(nbx_out + size_t(L.pp[e * Nfq + (n - Nq)]) * 4) = val;
+    }
     bad |= bad_value(h, v2, v3);
   }
   if (bad) atomicOr(flag, 1);
@@ -339,22 +348,10 @@ __device__ __forceinline__ void fetch_tile(const StageArgs &a, const InstDesc &d
   async_copy_words(lwords(L.wJ), words(static_cast<const real *>(d.wJq) + size_t(k0) * Nq), ne * Nq * W);
   async_copy_words(lwords(L.bq), words(static_cast<const real *>(d.bq) + size_t(k0) * Nq), ne * Nq * W);
   async_copy_words(lwords(L.bh), words(static_cast<const real *>(d.bh) + size_t(k0) * Nh), ne * Nh * W);
-  if (a.mode != kProject) {
-    // neighbour values: LDS word j of nb[(e*Nfq + f)*4 + c] comes from plane c at mapP
-    const uint32_t *ut = words(d.ut[a.in_buf]);
-    const int32_t *mapP = d.mapP + size_t(k0) * Nfq;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    const int nwords = ne * Nfq * 4 * W;
-    uint32_t *dst = lwords(L.nb);
-    for (int c0 = wave * 64; c0 < nwords; c0 += nwaves * 64) {
-      const int j = c0 + lane;
-      if (j < nwords) {
-        const int i = j / (4 * W), c = (j / W) % 4, w = j % W;
-        const size_t src = (size_t(c) * plane + size_t(mapP[i])) * W + w;
-        __builtin_amdgcn_global_load_lds((gptr_t)(ut + src), (lptr_t)(dst + c0), 4, 0, 0);
-      }
-    }
-  }
+  async_copy_words(reinterpret_cast<uint32_t *>(L.pp), words(d.pushP + size_t(k0) * Nfq), ne * Nfq);
+  if (a.mode != kProject)          // neighbour values, pushed here by the neighbours' projections
+    async_copy_words(lwords(L.nb), words(static_cast<const real *>(d.nbx[a.in_buf]) + size_t(k0) * Nfq * 4),
+                     ne * Nfq * 4 * W);
   __builtin_amdgcn_s_waitcnt(0);   // this wave's copies have landed in LDS
 }
 
@@ -370,20 +367,24 @@ __device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int 
   const int m0 = FACE ? Nq + r0 : r0;         // first hybrid-node index
   const real *Stab = FACE ? L.FT : L.ST;
   const real g = real(d.g);
+  typedef real real4 __attribute__((ext_vector_type(4)));
   const real *rbase = L.rec + e * Nh * kNodeRec;
   real hu[R], hv[R], u[R], v[R], gh[R], rx[R], sx[R], ry[R], sy[R], a0[R], a1[R], a2[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const real *rm = rbase + (m0 + r) * kNodeRec;
-    hu[r] = rm[0]; hv[r] = rm[1]; u[r] = rm[2]; v[r] = rm[3]; gh[r] = rm[4];
-    rx[r] = rm[6]; sx[r] = rm[7]; ry[r] = rm[8]; sy[r] = rm[9];
+    const real4 s0 = *reinterpret_cast<const real4 *>(rm), s1 = *reinterpret_cast<const real4 *>(rm + 4);
+    hu[r] = s0.x; hv[r] = s0.y; u[r] = s0.z; v[r] = s0.w;
+    rx[r] = s1.x; sx[r] = s1.y; ry[r] = s1.z; sy[r] = s1.w;
+    gh[r] = rm[8];
     a0[r] = 0; a1[r] = 0; a2[r] = 0;
   }
 #pragma unroll 2
   for (int n = n_lo; n < n_hi; ++n) {
     const real *rn = rbase + n * kNodeRec;
-    const real hun = rn[0], hvn = rn[1], un = rn[2], vn = rn[3], dHn = rn[5];
-    const real rxn = rn[6], sxn = rn[7], ryn = rn[8], syn = rn[9];
+    const real4 c0 = *reinterpret_cast<const real4 *>(rn), c1 = *reinterpret_cast<const real4 *>(rn + 4);
+    const real hun = c0.x, hvn = c0.y, un = c0.z, vn = c0.w, dHn = rn[9];
+    const real rxn = c1.x, sxn = c1.y, ryn = c1.z, syn = c1.w;
     const real *S = Stab + (n * LD + r0) * 2;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -406,7 +407,7 @@ __device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int 
       const real *rm = rbase + m * kNodeRec;
       const real wf = L.wf[f], nrf = L.nr[f], nsf = L.ns[f];
       const real nJx = rx[r] * nrf + sx[r] * nsf, nJy = ry[r] * nrf + sy[r] * nsf;
-      const real h = rm[10], uu = real(2) * u[r], vv = real(2) * v[r], dH = rm[5];
+      const real h = rm[10], uu = real(2) * u[r], vv = real(2) * v[r], dH = rm[9];
       const real huu = real(2) * hu[r], hvv = real(2) * hv[r];
       const real *nbp = L.nb + (e * Nfq + f) * 4;
       const real hP = nbp[0], uP = nbp[1], vP = nbp[2], dHP = nbp[3];
@@ -468,25 +469,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
   fetch_tile<real, N>(a, d, k0, ne, L);
   if (a.mode == kProject) {
     __syncthreads();
-    project_tile<real, N, CM>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]), a.flag);
+    project_tile<real, N, CM>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]),
+                              static_cast<real *>(d.nbx[a.out_buf]), a.flag);
     return;
   }
   __syncthreads();
   // phase 1: node records from the fetched u~ and metric factors
   for (int i = tid; i < ne * Nh; i += nth) {
     const real h = L.raw[i], u = L.raw[ne * Nh + i], v = L.raw[2 * ne * Nh + i], dH = L.raw[3 * ne * Nh + i];
-    real *rec = L.rec + i * kNodeRec;
-    rec[0] = real(0.5) * h * u;
-    rec[1] = real(0.5) * h * v;
-    rec[2] = real(0.5) * u;
-    rec[3] = real(0.5) * v;
-    rec[4] = real(0.5) * g * h;
-    rec[5] = dH;
-    rec[6] = L.raw[4 * ne * Nh + i];
-    rec[7] = L.raw[5 * ne * Nh + i];
-    rec[8] = L.raw[6 * ne * Nh + i];
-    rec[9] = L.raw[7 * ne * Nh + i];
-    rec[10] = h;
+    typedef real real4 __attribute__((ext_vector_type(4)));
+    real4 *rec = reinterpret_cast<real4 *>(L.rec + i * kNodeRec);
+    rec[0] = real4{real(0.5) * h * u, real(0.5) * h * v, real(0.5) * u, real(0.5) * v};
+    rec[1] = real4{L.raw[4 * ne * Nh + i], L.raw[5 * ne * Nh + i], L.raw[6 * ne * Nh + i], L.raw[7 * ne * Nh + i]};
+    rec[2] = real4{real(0.5) * g * h, dH, h, real(0)};
   }
   __syncthreads();
   residual_tile<real, N, R, ColParts<N>::value>(d, ne, L);
@@ -520,41 +515,48 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
   real *du = static_cast<real *>(d.du);
   real *rhs_out = static_cast<real *>(a.ext_rhs);
   const real ra = real(a.rk_a), rdt = real(d.dt), rb = real(a.rk_b);
-  for (int i = tid; i < ne * Np; i += nth) {
-    const int e = i / Np, row = i - e * Np;
+  // one task per (field, element, mode)
+  for (int i = tid; i < 3 * ne * Np; i += nth) {
+    const int c = i / (ne * Np), j = i - c * ne * Np, e = j / Np, row = j - e * Np;
     const real *Mi = L.Minv + (e * Np + row) * Np;
-    real r0 = 0, r1 = 0, r2 = 0;
+    const real *Tc = L.T + c * ne * Np + e * Np;
+    real ra0 = 0, ra1 = 0;
 #pragma unroll 4
-    for (int j = 0; j < Np; ++j) {
-      const real mm = Mi[j];
-      r0 -= mm * L.T[0 * ne * Np + e * Np + j];
-      r1 -= mm * L.T[1 * ne * Np + e * Np + j];
-      r2 -= mm * L.T[2 * ne * Np + e * Np + j];
+    for (int m = 0; m + 1 < Np; m += 2) {
+      ra0 -= Mi[m] * Tc[m];
+      ra1 -= Mi[m + 1] * Tc[m + 1];
     }
-    const size_t o = size_t(k0) * Np + i;
+    if (Np & 1) ra0 -= Mi[Np - 1] * Tc[Np - 1];
+    const real rr = ra0 + ra1;
+    const size_t o = size_t(c) * splane + size_t(k0) * Np + j;
     if (a.mode == kRhs) {
-      rhs_out[o] = r0;
-      rhs_out[splane + o] = r1;
-      rhs_out[2 * splane + o] = r2;
+      rhs_out[o] = rr;
     } else {
-      const real rr[3] = {r0, r1, r2};
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const real dn = ra * L.DU[c * ne * Np + i] + rdt * rr[c];
-        const real un = L.U[c * ne * Np + i] + rb * dn;
-        du[c * splane + o] = dn;
-        uh[c * splane + o] = un;
-        L.U[c * ne * Np + i] = un;
-      }
+      const real dn = ra * L.DU[i] + rdt * rr;
+      const real un = L.U[i] + rb * dn;
+      du[o] = dn;
+      uh[o] = un;
+      L.U[i] = un;
     }
   }
   if (a.mode == kStage) {
     __syncthreads();
-    project_tile<real, N, CM>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]), a.flag);
+    project_tile<real, N, CM>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]),
+                              static_cast<real *>(d.nbx[a.out_buf]), a.flag);
   }
 }
 
 
+
+// Descriptors, tiles and tile ranges are written by the host before a launch and only
+// read by kernels.  Reading them through the constant address space lets the compiler use
+// scalar loads (lgkmcnt); as vector loads they would share vmcnt with the asynchronous
+// LDS copies, and every descriptor field needed between two copies would wait for all
+// copies issued before it.
+template <typename T>
+__device__ __forceinline__ const T &read_const(const T *p, int i) {
+  return *(const T *)((const __attribute__((address_space(4))) T *)p + i);
+}
 
 // Persistent stage kernel: block b walks a contiguous range of tiles.  Blocks are dealt
 // to the XCDs round-robin, so block b's range is chosen as range number
@@ -562,18 +564,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
 // and face neighbours written by the previous stage tend to sit in its L2.  The
 // reference-operator block stays in LDS and is reloaded only when the degree changes.
 template <typename real, int CM>
-__global__ void __launch_bounds__(kBlock, 2) stage_kernel(StageArgs a) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 ? 4 : 2)))
+stage_kernel(StageArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   real *sm = reinterpret_cast<real *>(smem_raw);
   real *tile = sm + a.ref_words_max;
   const int G = int(gridDim.x);
   const int chunk = (int(blockIdx.x) % kXcds) * (G / kXcds) + int(blockIdx.x) / kXcds;
-  const int t0 = a.ranges ? a.ranges[chunk] : int((long long)chunk * a.ntiles / G);
-  const int t1 = a.ranges ? a.ranges[chunk + 1] : int((long long)(chunk + 1) * a.ntiles / G);
+  const int t0 = a.ranges ? read_const(a.ranges, chunk) : int((long long)chunk * a.ntiles / G);
+  const int t1 = a.ranges ? read_const(a.ranges, chunk + 1) : int((long long)(chunk + 1) * a.ntiles / G);
   int loaded_N = 0;
   for (int t = t0; t < t1; ++t) {
-    const Tile tl = a.tiles[t];
-    const InstDesc &d = a.desc[tl.inst];
+    const Tile tl = read_const(a.tiles, t);
+    const InstDesc &d = read_const(a.desc, tl.inst);
     if (d.N != loaded_N) {
       __syncthreads();
       const real *ref = static_cast<const real *>(d.ref);
@@ -632,8 +635,8 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagArgs a) {
   __shared__ double red[kBlock][6];
   const int t = blockIdx.x;
   if (t >= a.ntiles) return;
-  const Tile tl = a.tiles[t];
-  const InstDesc &d = a.desc[tl.inst];
+  const Tile tl = read_const(a.tiles, t);
+  const InstDesc &d = read_const(a.desc, tl.inst);
   double acc[6] = {0, 0, 0, 0, 0, 0};
   switch (d.N) {
     case 1: diag_tile<real, 1>(d, tl.k0, tl.ne, acc); break;

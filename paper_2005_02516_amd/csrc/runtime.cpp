@@ -53,7 +53,7 @@ int default_epb(int N, size_t word) {
 }
 
 struct Offsets {
-  size_t uh, du, ut[3], geo, wJq, Minv, bq, bh, mapP, rhs;
+  size_t uh, du, ut[3], nbx[3], geo, wJq, Minv, bq, bh, pushP, rhs;
 };
 
 }  // namespace
@@ -161,7 +161,7 @@ StageArgs base_args(esdg_swe *s, int inst) {
     a.ntiles = s->tile_count[inst];
   }
   a.flag = s->dev<int32_t>(s->flag_off);
-  a.ref_words_max = s->ref_max;
+  a.ref_words_max = s->ref_max;   // a multiple of 4: node records stay 16-byte aligned
   a.contraction = s->contraction;
   return a;
 }
@@ -282,6 +282,7 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
     s->ref_max = std::max(s->ref_max, ref_words(N));
     tile = std::max(tile, size_t(tile_words(N, E)));
   }
+  s->ref_max = (s->ref_max + 3) & ~3;
   size_t lds = (size_t(s->ref_max) + tile) * s->word;
   if (lds > 160 * 1024) {
     g_init_error = "esdg_swe_init: elems_per_block needs more than 160 KiB of LDS";
@@ -313,12 +314,13 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
     f.uh = take(3 * K * Np * w);
     f.du = take(3 * K * Np * w);
     for (int b = 0; b < 3; ++b) f.ut[b] = take(4 * K * Nh * w);
+    for (int b = 0; b < 3; ++b) f.nbx[b] = take(4 * K * Nfq * w);
     f.geo = take(4 * K * Nh * w);
     f.wJq = take(K * Nq * w);
     f.Minv = take(K * Np * Np * w);
     f.bq = take(K * Nq * w);
     f.bh = take(K * Nh * w);
-    f.mapP = take(K * Nfq * 4);
+    f.pushP = take(K * Nfq * 4);
     f.rhs = take(3 * K * Np * w);
   }
   s->tiles_off = take(s->tiles.size() * sizeof(Tile));
@@ -375,7 +377,24 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
     if ((st = upload(s, f.bq, keep.back().data(), keep.back().size()))) return st;
     keep.push_back(to_bulk(H.bh, s->fp64));
     if ((st = upload(s, f.bh, keep.back().data(), keep.back().size()))) return st;
-    if ((st = upload(s, f.mapP, H.mapP.data(), H.mapP.size() * 4))) return st;
+    {
+      // face node f of element k fills slot k' * Nfq + f' of the neighbour's face list
+      const int Nh = dim_Nh(H.N), Nq = dim_Nq(H.N), Nfq = dim_Nfq(H.N);
+      std::vector<int32_t> push(H.mapP.size());
+      for (size_t j = 0; j < push.size(); ++j) {
+        const int32_t m = H.mapP[j], k2 = m / Nh;
+        push[j] = k2 * Nfq + (m - k2 * Nh - Nq);
+      }
+      // inverse-permutation check: every slot is filled exactly once
+      std::vector<char> hit(push.size(), 0);
+      for (int32_t p : push) {
+        if (p < 0 || size_t(p) >= push.size() || hit[p]) return s->fail(ESDG_EMESH, "face push map is not a permutation");
+        hit[p] = 1;
+      }
+      keep.push_back(std::vector<unsigned char>(reinterpret_cast<unsigned char *>(push.data()),
+                                                reinterpret_cast<unsigned char *>(push.data() + push.size())));
+      if ((st = upload(s, f.pushP, keep.back().data(), keep.back().size()))) return st;
+    }
     InstDesc &d = s->desc[i];
     d.N = H.N;
     d.K = H.K;
@@ -386,12 +405,13 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
     d.uh = s->ws + f.uh;
     d.du = s->ws + f.du;
     for (int b = 0; b < 3; ++b) d.ut[b] = s->ws + f.ut[b];
+    for (int b = 0; b < 3; ++b) d.nbx[b] = s->ws + f.nbx[b];
     d.geo = s->ws + f.geo;
     d.wJq = s->ws + f.wJq;
     d.Minv = s->ws + f.Minv;
     d.bq = s->ws + f.bq;
     d.bh = s->ws + f.bh;
-    d.mapP = s->dev<int32_t>(f.mapP);
+    d.pushP = s->dev<int32_t>(f.pushP);
     d.ref = s->ws + s->ref_off[H.N];
     d.rhs_scratch = s->ws + f.rhs;
   }
