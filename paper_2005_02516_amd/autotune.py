@@ -19,7 +19,7 @@ from typing import Dict, Iterable, List, Optional, Tuple
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tune_cache_gfx950.json")
-CANDIDATES = (1, 2, 4, 8, 16, 32)
+CANDIDATES = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32)
 
 
 def size_class(K: int) -> str:

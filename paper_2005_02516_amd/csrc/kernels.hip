@@ -24,6 +24,7 @@
 // constant), so the projection works on v1 - g Href and no quantity of size g H is
 // rounded to the bulk precision; the conversions to h are done in double.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 
 #include <cmath>
 #include <type_traits>
@@ -35,6 +36,10 @@ namespace esdg {
 __device__ inline bool bad_value(double h, double a, double b) {
   return !(h > 0.0) || !isfinite(h) || !isfinite(a) || !isfinite(b);
 }
+
+// The wave's index in the workgroup, as a wave-uniform (scalar) value: loops over
+// wave-sized chunks then keep their counters, bounds and LDS bases in scalar registers.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6); }
 
 // ---------------------------------------------------------------- matrix-core contractions
 // C[M x NC] = A[M x KD] B[KD x NC], A and B read from LDS, on the matrix cores.  One wave
@@ -63,7 +68,7 @@ __device__ inline float bf16_value(unsigned short h) { return __uint_as_float(un
 
 template <int MODE, typename real, class FA, class FB, class FC>
 __device__ __forceinline__ void gemm_mfma(int M, int KD, int NC, FA a_at, FB b_at, FC c_store) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id(), nwaves = blockDim.x >> 6;
   const int mb = (M + 15) / 16, nb = (NC + 15) / 16;
   const int lrow = lane & 15, quad = lane >> 4;
 #pragma unroll 1
@@ -214,7 +219,7 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
     }
     const double eta = u0, hu = u1, hv = u2;
     const double h = eta + Href - double(L.bq[i]);
-    const double uu = hu / h, vv = hv / h;
+    const double rh = 1.0 / h, uu = hu * rh, vv = hv * rh;
     const double v1 = g * eta - 0.5 * (uu * uu + vv * vv);
     const double w = L.wJ[i];
     L.Q[0 * ne * Nq + i] = real(w * v1);
@@ -230,7 +235,7 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
                   [&](int i, int c, real v) { L.T[c * Np + i] = v; });
   }
   for (int i = tid; i < 3 * ne * Np && !mfma; i += nth) {
-    const int c = i / (ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
+    const int c = (i >= ne * Np) + (i >= 2 * ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
     const real *Qc = L.Q + c * ne * Nq + e * Nq;
     real ya = 0, yb = 0;
 #pragma unroll 4
@@ -244,7 +249,7 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
   __syncthreads();
   // v'_h = Minv_k y
   for (int i = tid; i < 3 * ne * Np; i += nth) {
-    const int c = i / (ne * Np), r = i - c * ne * Np, e = r / Np, row = r - e * Np;
+    const int c = (i >= ne * Np) + (i >= 2 * ne * Np), r = i - c * ne * Np, e = r / Np, row = r - e * Np;
     const real *Mi = L.Minv + (e * Np + row) * Np;
     const real *Tc = L.T + c * ne * Np + e * Np;
     real va = 0, vb = 0;
@@ -303,12 +308,13 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
 // Asynchronous global -> LDS copies (global_load_lds_dword): each lane moves one 32-bit
 // word straight into LDS at (wave-uniform base) + 4 * lane, so a wave copies 64
 // consecutive words per instruction without staging them in registers; completion is
-// awaited once, with s_waitcnt vmcnt(0), before the tile's barrier.
+// awaited once, with s_waitcnt vmcnt(0), before the tile's barrier.  (The 16-byte form,
+// global_load_lds_dwordx4, measured slower for these tile fetches.)
 typedef __attribute__((address_space(1))) const void *gptr_t;
 typedef __attribute__((address_space(3))) void *lptr_t;
 
 __device__ inline void async_copy_words(uint32_t *dst, const uint32_t *src, int nwords) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id(), nwaves = blockDim.x >> 6;
   for (int c = wave * 64; c < nwords; c += nwaves * 64) {
     if (c + lane < nwords)
       __builtin_amdgcn_global_load_lds((gptr_t)(src + c + lane), (lptr_t)(dst + c), 4, 0, 0);
@@ -497,7 +503,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
     }
   }
   for (int i = tid; i < 3 * ne * Np && !mfma; i += nth) {
-    const int c = i / (ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
+    const int c = (i >= ne * Np) + (i >= 2 * ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
     const real *Rc = L.R + c * ne * Nh + e * Nh;
     real ya = 0, yb = 0;
 #pragma unroll 4
@@ -517,7 +523,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
   const real ra = real(a.rk_a), rdt = real(d.dt), rb = real(a.rk_b);
   // one task per (field, element, mode)
   for (int i = tid; i < 3 * ne * Np; i += nth) {
-    const int c = i / (ne * Np), j = i - c * ne * Np, e = j / Np, row = j - e * Np;
+    const int c = (i >= ne * Np) + (i >= 2 * ne * Np), j = i - c * ne * Np, e = j / Np, row = j - e * Np;
     const real *Mi = L.Minv + (e * Np + row) * Np;
     const real *Tc = L.T + c * ne * Np + e * Np;
     real ra0 = 0, ra1 = 0;
@@ -677,6 +683,14 @@ hipError_t stage_max_blocks(bool fp64, int cm, size_t lds_bytes, int *out) {
   if (e != hipSuccess) return e;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_fn(fp64, cm), kBlock, lds_bytes);
   if (e != hipSuccess) return e;
+  // The occupancy query does not round the LDS request up to the allocation granule; a
+  // workgroup count it reports can then fail to fit, and the persistent grid's surplus
+  // blocks only start when others finish.  Cap it with 1 KiB granules of the CU's LDS.
+  int lds_cu = 0;
+  e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+  if (e != hipSuccess) return e;
+  const size_t granule = 1024, need = (lds_bytes + granule - 1) / granule * granule;
+  if (need > 0 && lds_cu > 0) per_cu = std::min<long long>(per_cu, (long long)(size_t(lds_cu) / need));
   *out = ncu * (per_cu > 0 ? per_cu : 1);
   return hipSuccess;
 }
