@@ -45,6 +45,18 @@ __host__ __device__ constexpr int tile_words(int N, int E) {
                              dim_Np(N) * dim_Np(N) + 2 * dim_Nq(N) + dim_Nh(N) + dim_Nfq(N));
 }
 
+// Reals per element of the static per-tile block (see InstDesc::stat): Minv, w J, b at the
+// volume and at the hybrid nodes, and the face push targets (int32, one real-sized slot each).
+__host__ __device__ constexpr int stat_words(int N) {
+  return dim_Np(N) * dim_Np(N) + 2 * dim_Nq(N) + dim_Nh(N) + dim_Nfq(N);
+}
+
+// 32-bit words per thread of the static block that a stage stages through registers
+// (issued after the tile's other copies have landed, stored to LDS after the residual),
+// for float and for double tiles.
+constexpr int kStatRegs = 8;
+template <typename real> struct StatRegs { static constexpr int value = sizeof(real) == 4 ? kStatRegs : 4; };
+
 // One instance as the kernels see it (device pointers into the bound workspace).
 struct InstDesc {
   int32_t N, K, flux, pad0;
@@ -55,11 +67,12 @@ struct InstDesc {
   void *nbx[3];        // [K][Nfq][4] the same four values at each face node's neighbour, written
                        // by the neighbour's projection (one per ut buffer)
   const void *geo;     // [4][K][Nh] rxJ, sxJ, ryJ, syJ
-  const void *wJq;     // [K][Nq] w_q J
-  const void *Minv;    // [K][Np][Np]
-  const void *bq;      // [K][Nq] bathymetry at volume nodes
-  const void *bh;      // [K][Nh] bathymetry at hybrid nodes
-  const int32_t *pushP; // [K][Nfq] slot k'*Nfq + f' of nbx that face node f of element k fills
+  const void *wJq;     // [K][Nq] w_q J (diagnostics)
+  const void *bq;      // [K][Nq] bathymetry at volume nodes (diagnostics)
+  const void *stat;    // static data in tile order: the tile of elements k0..k0+ne-1 holds, from
+                       // real k0 * stat_words(N): Minv [ne][Np][Np] | w J [ne][Nq] | b [ne][Nq] |
+                       // b [ne][Nh] | push targets [ne][Nfq] (int32 k'*Nfq + f' of the nbx slot
+                       // that face node f fills, packed in the first ne*Nfq 32-bit words)
   const void *ref;     // reference-operator block for this N
   void *rhs_scratch;   // [3][K][Np] used by the diagnostics
 };

@@ -321,6 +321,13 @@ __device__ inline void async_copy_words(uint32_t *dst, const uint32_t *src, int 
   }
 }
 
+// 32-bit words of a tile's static block staged through registers during a stage.
+template <typename real>
+__device__ __forceinline__ int stat_head(int nstat) {
+  constexpr int cap = StatRegs<real>::value * kBlock;
+  return nstat < cap ? nstat : cap;
+}
+
 // Phase 0: fetch the tile's global data into LDS (all asynchronous; see above).
 template <typename real, int N>
 __device__ __forceinline__ void fetch_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, Lds<real, N> &L) {
@@ -350,11 +357,14 @@ __device__ __forceinline__ void fetch_tile(const StageArgs &a, const InstDesc &d
     for (int c = 0; c < 3; ++c)
       async_copy_words(lwords(L.U + c * ne * Np), words(src + c * splane + size_t(k0) * Np), ne * Np * W);
   }
-  async_copy_words(lwords(L.Minv), words(static_cast<const real *>(d.Minv) + size_t(k0) * Np * Np), ne * Np * Np * W);
-  async_copy_words(lwords(L.wJ), words(static_cast<const real *>(d.wJq) + size_t(k0) * Nq), ne * Nq * W);
-  async_copy_words(lwords(L.bq), words(static_cast<const real *>(d.bq) + size_t(k0) * Nq), ne * Nq * W);
-  async_copy_words(lwords(L.bh), words(static_cast<const real *>(d.bh) + size_t(k0) * Nh), ne * Nh * W);
-  async_copy_words(reinterpret_cast<uint32_t *>(L.pp), words(d.pushP + size_t(k0) * Nfq), ne * Nfq);
+  {
+    // static block (Minv, w J, b, push targets): contiguous in HBM and in LDS.  A stage
+    // copies only the part beyond the first kStatRegs * kBlock words here; that head goes
+    // through registers and lands in LDS after the residual (stage_tile).
+    const int nstat = ne * stat_words(N) * W, head = a.mode == kProject ? 0 : stat_head<real>(nstat);
+    async_copy_words(lwords(L.Minv) + head, words(static_cast<const real *>(d.stat) + size_t(k0) * stat_words(N)) + head,
+                     nstat - head);
+  }
   if (a.mode != kProject)          // neighbour values, pushed here by the neighbours' projections
     async_copy_words(lwords(L.nb), words(static_cast<const real *>(d.nbx[a.in_buf]) + size_t(k0) * Nfq * 4),
                      ne * Nfq * 4 * W);
@@ -473,6 +483,20 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
   Lds<real, N> L(sm, tile, ne);
   const real g = real(d.g);
   fetch_tile<real, N>(a, d, k0, ne, L);
+  // head of the static block: loaded into registers now, while the node records and the
+  // residual run, and written to LDS before the barrier that ends the residual
+  constexpr int W = sizeof(real) / 4;
+  const int nstat = ne * stat_words(N) * W, head = stat_head<real>(nstat);
+  constexpr int SR = StatRegs<real>::value;
+  const uint32_t *sg = static_cast<const uint32_t *>(d.stat) + size_t(k0) * stat_words(N) * W;
+  uint32_t sreg[SR];
+  if (a.mode != kProject) {
+#pragma unroll
+    for (int j = 0; j < SR; ++j) {
+      const int v = tid + j * kBlock;
+      sreg[j] = v < head ? sg[v] : 0u;
+    }
+  }
   if (a.mode == kProject) {
     __syncthreads();
     project_tile<real, N, CM>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]),
@@ -491,6 +515,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
   }
   __syncthreads();
   residual_tile<real, N, R, ColParts<N>::value>(d, ne, L);
+  {
+    uint32_t *sl = reinterpret_cast<uint32_t *>(L.Minv);
+#pragma unroll
+    for (int j = 0; j < SR; ++j) {
+      const int v = tid + j * kBlock;
+      if (v < head) sl[v] = sreg[j];
+    }
+  }
   __syncthreads();
   // lift: y = V_h^T r_h (r_h = sum of the P partials), one task per (field, element, mode)
   constexpr bool mfma = CM != kValu;
@@ -570,7 +602,7 @@ __device__ __forceinline__ const T &read_const(const T *p, int i) {
 // and face neighbours written by the previous stage tend to sit in its L2.  The
 // reference-operator block stays in LDS and is reloaded only when the degree changes.
 template <typename real, int CM>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 ? 4 : 2)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel(StageArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   real *sm = reinterpret_cast<real *>(smem_raw);

@@ -53,7 +53,7 @@ int default_epb(int N, size_t word) {
 }
 
 struct Offsets {
-  size_t uh, du, ut[3], nbx[3], geo, wJq, Minv, bq, bh, pushP, rhs;
+  size_t uh, du, ut[3], nbx[3], geo, wJq, bq, stat, rhs;
 };
 
 }  // namespace
@@ -317,10 +317,8 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
     for (int b = 0; b < 3; ++b) f.nbx[b] = take(4 * K * Nfq * w);
     f.geo = take(4 * K * Nh * w);
     f.wJq = take(K * Nq * w);
-    f.Minv = take(K * Np * Np * w);
     f.bq = take(K * Nq * w);
-    f.bh = take(K * Nh * w);
-    f.pushP = take(K * Nfq * 4);
+    f.stat = take(K * size_t(stat_words(N)) * w);
     f.rhs = take(3 * K * Np * w);
   }
   s->tiles_off = take(s->tiles.size() * sizeof(Tile));
@@ -371,15 +369,11 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
     if ((st = upload(s, f.geo, keep.back().data(), keep.back().size()))) return st;
     keep.push_back(to_bulk(H.wJq, s->fp64));
     if ((st = upload(s, f.wJq, keep.back().data(), keep.back().size()))) return st;
-    keep.push_back(to_bulk(H.Minv, s->fp64));
-    if ((st = upload(s, f.Minv, keep.back().data(), keep.back().size()))) return st;
     keep.push_back(to_bulk(H.bq, s->fp64));
     if ((st = upload(s, f.bq, keep.back().data(), keep.back().size()))) return st;
-    keep.push_back(to_bulk(H.bh, s->fp64));
-    if ((st = upload(s, f.bh, keep.back().data(), keep.back().size()))) return st;
     {
       // face node f of element k fills slot k' * Nfq + f' of the neighbour's face list
-      const int Nh = dim_Nh(H.N), Nq = dim_Nq(H.N), Nfq = dim_Nfq(H.N);
+      const int Np = dim_Np(H.N), Nh = dim_Nh(H.N), Nq = dim_Nq(H.N), Nfq = dim_Nfq(H.N);
       std::vector<int32_t> push(H.mapP.size());
       for (size_t j = 0; j < push.size(); ++j) {
         const int32_t m = H.mapP[j], k2 = m / Nh;
@@ -391,9 +385,28 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
         if (p < 0 || size_t(p) >= push.size() || hit[p]) return s->fail(ESDG_EMESH, "face push map is not a permutation");
         hit[p] = 1;
       }
-      keep.push_back(std::vector<unsigned char>(reinterpret_cast<unsigned char *>(push.data()),
-                                                reinterpret_cast<unsigned char *>(push.data() + push.size())));
-      if ((st = upload(s, f.pushP, keep.back().data(), keep.back().size()))) return st;
+      // static blocks in tile order (the layout of the tile's LDS region from Minv on)
+      const size_t SW = size_t(stat_words(H.N)), word = s->word;
+      std::vector<unsigned char> blk(size_t(H.K) * SW * word, 0);
+      auto put = [&](size_t real_index, double v) {
+        if (s->fp64) std::memcpy(&blk[real_index * 8], &v, 8);
+        else { const float f32 = float(v); std::memcpy(&blk[real_index * 4], &f32, 4); }
+      };
+      for (int t = s->tile_begin[i]; t < s->tile_begin[i] + s->tile_count[i]; ++t) {
+        const int k0 = s->tiles[t].k0, ne = s->tiles[t].ne;
+        size_t o = size_t(k0) * SW;
+        for (int e = 0; e < ne; ++e)
+          for (int j = 0; j < Np * Np; ++j) put(o++, H.Minv[size_t(k0 + e) * Np * Np + j]);
+        for (int e = 0; e < ne; ++e)
+          for (int q = 0; q < Nq; ++q) put(o++, H.wJq[size_t(k0 + e) * Nq + q]);
+        for (int e = 0; e < ne; ++e)
+          for (int q = 0; q < Nq; ++q) put(o++, H.bq[size_t(k0 + e) * Nq + q]);
+        for (int e = 0; e < ne; ++e)
+          for (int n = 0; n < Nh; ++n) put(o++, H.bh[size_t(k0 + e) * Nh + n]);
+        std::memcpy(&blk[o * word], &push[size_t(k0) * Nfq], size_t(ne) * Nfq * 4);
+      }
+      keep.push_back(std::move(blk));
+      if ((st = upload(s, f.stat, keep.back().data(), keep.back().size()))) return st;
     }
     InstDesc &d = s->desc[i];
     d.N = H.N;
@@ -408,10 +421,8 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
     for (int b = 0; b < 3; ++b) d.nbx[b] = s->ws + f.nbx[b];
     d.geo = s->ws + f.geo;
     d.wJq = s->ws + f.wJq;
-    d.Minv = s->ws + f.Minv;
     d.bq = s->ws + f.bq;
-    d.bh = s->ws + f.bh;
-    d.pushP = s->dev<int32_t>(f.pushP);
+    d.stat = s->ws + f.stat;
     d.ref = s->ws + s->ref_off[H.N];
     d.rhs_scratch = s->ws + f.rhs;
   }
