@@ -129,6 +129,7 @@ class EsdgSwe:
             elems_per_block = lookup(precision, [(w.N, w.K) for w in instances])
         if matrix_cores is None:
             matrix_cores = os.environ.get("ESDG_SWE_MATRIX_CORES", "0") == "1"
+        self.elems_per_block = elems_per_block
         opt = make_options(precision, flux, g, use_graph, elems_per_block, matrix_cores)
         h = C.c_void_p()
         nbytes = C.c_size_t()
