@@ -140,7 +140,7 @@ def ensemble(args, torch):
     for prec in ([args.precision] + ([] if args.no_fp64 else ["fp64"])):
         t0 = time.perf_counter()
         s = EsdgSwe(ws, precision=prec, flux="lf", g=1.0, use_graph=not args.no_graph,
-                    matrix_cores=args.matrix_cores)
+                    matrix_cores=args.matrix_cores, fused=args.fused)
         for i, w in enumerate(ws):
             s.set_state(i, w.u_nodes)
         print(f"# {prec}: planned and set in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -180,6 +180,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--fused", action="store_true",
+                    help="all RK stages of the timed steps in one cooperative launch (neighbour-tile waits)")
     ap.add_argument("--matrix-cores", action="store_true",
                     help="projection/lift contractions on the matrix cores in the bulk precision")
     ap.add_argument("--ensemble", type=int, default=0,
@@ -218,7 +220,7 @@ def main():
     precs = [args.precision] + ([] if args.no_fp64 or args.precision == "fp64" else ["fp64"])
     for prec in precs:
         s = EsdgSwe([w], precision=prec, flux=w.flux, g=w.g, elems_per_block=args.epb, use_graph=not args.no_graph,
-                    matrix_cores=args.matrix_cores)
+                    matrix_cores=args.matrix_cores, fused=args.fused)
         e = s.elems_per_block
         epb_used[prec] = int(e.get(w.N, 0)) if isinstance(e, dict) else int(e or 0)
         s.set_state(0, w.u_nodes)
@@ -282,7 +284,8 @@ def main():
                                f"N={w.N} (Np={Np}, Nq={Nq}, Nfq={Nfq}), LF flux, LSRK4(5)",
                    "K": w.K, "N": w.N, "DOF": dof, "precision": prec, "hip_graph": not args.no_graph,
                    "elements_per_workgroup": epb_used.get(prec, 0),
-                   "matrix_cores": bool(args.matrix_cores or prec == "bf16x3")},
+                   "matrix_cores": bool(args.matrix_cores or prec == "bf16x3"),
+                   "fused_steps": bool(args.fused)},
         "roofline": roof,
     }
     if "fp64" in results and prec != "fp64":

@@ -105,6 +105,12 @@ typedef struct {
   int32_t matrix_cores;     /* projection/lift contractions with constant operators: 0 or 1 =
                                vector ALUs, 2 = matrix cores (MFMA) in the bulk precision;
                                ESDG_FP32_BF16X3 always uses the split-bf16 matrix-core path  */
+  int32_t fused_steps;      /* nonzero: esdg_swe_step runs all its RK stages in one
+                               cooperative launch, each element tile starting a stage once
+                               the tiles of its face neighbours have finished the previous
+                               one (no grid-wide barrier; use_graph is then ignored).  Bind
+                               fails with ESDG_EDEVICE where cooperative launch is missing.
+                               Results are bitwise those of the per-stage launches.           */
 } esdg_swe_options;
 
 /* Plan a solver for n_inst independent instances (n_inst = 1 for a single run).  Builds,
@@ -148,8 +154,10 @@ esdg_status esdg_swe_rhs(esdg_swe *s, int32_t inst, const void *state_dev, void 
 /* Advance every instance by nsteps LSRK4(5) steps (5 RHS evaluations each, Section 4).
  * dt is a host array with one time step per instance.  Asynchronous on the bound stream:
  * one kernel launch per RK stage for all instances together, replayed from HIP graphs
- * when use_graph is set.  Non-physical states are reported by the next synchronising
- * call (get_state, diagnostics, sync). */
+ * when use_graph is set, or one cooperative launch for all nsteps stages when fused_steps
+ * is set.  Non-physical states (ESDG_ENONPHYS) and a fused launch whose neighbour wait
+ * gave up (ESDG_EDEVICE; the state is then undefined) are reported by the next
+ * synchronising call (get_state, diagnostics, sync). */
 esdg_status esdg_swe_step(esdg_swe *s, const double *dt, int32_t nsteps);
 
 /* Per-instance FP64 diagnostics of the current state, out = host [n_inst][6]:

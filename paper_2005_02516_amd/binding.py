@@ -35,11 +35,12 @@ class esdg_swe_instance(C.Structure):
 
 class esdg_swe_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("flux", C.c_int32), ("g", C.c_double),
-                ("use_graph", C.c_int32), ("elems_per_block", C.c_int32 * 6), ("matrix_cores", C.c_int32)]
+                ("use_graph", C.c_int32), ("elems_per_block", C.c_int32 * 6), ("matrix_cores", C.c_int32),
+                ("fused_steps", C.c_int32)]
 
 
 def make_options(precision: str, flux: str, g: float, use_graph: bool = True, epb=None,
-                 matrix_cores: bool = False) -> esdg_swe_options:
+                 matrix_cores: bool = False, fused: bool = False) -> esdg_swe_options:
     """epb: None, an int (all degrees) or a mapping N -> elements per workgroup."""
     arr = (C.c_int32 * 6)()
     if isinstance(epb, int):
@@ -49,7 +50,7 @@ def make_options(precision: str, flux: str, g: float, use_graph: bool = True, ep
         for N, E in epb.items():
             arr[int(N)] = int(E)
     return esdg_swe_options(PRECISIONS[precision], FLUXES[flux], float(g), int(use_graph), arr,
-                            2 if matrix_cores else 1)
+                            2 if matrix_cores else 1, 1 if fused else 0)
 
 
 class EsdgError(RuntimeError):
@@ -109,7 +110,7 @@ class EsdgSwe:
 
     def __init__(self, instances: Sequence, precision: str = "fp64", flux: str = "lf", g: float = 1.0,
                  elems_per_block=None, use_graph: bool = True, device: str = "cuda:0", stream=None,
-                 tuned: bool = True, matrix_cores: Optional[bool] = None):
+                 tuned: bool = True, matrix_cores: Optional[bool] = None, fused: Optional[bool] = None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("EsdgSwe needs a GPU: the library has no CPU path")
@@ -129,8 +130,11 @@ class EsdgSwe:
             elems_per_block = lookup(precision, [(w.N, w.K) for w in instances])
         if matrix_cores is None:
             matrix_cores = os.environ.get("ESDG_SWE_MATRIX_CORES", "0") == "1"
+        if fused is None:
+            fused = os.environ.get("ESDG_SWE_FUSED", "0") == "1"
         self.elems_per_block = elems_per_block
-        opt = make_options(precision, flux, g, use_graph, elems_per_block, matrix_cores)
+        self.fused = bool(fused)
+        opt = make_options(precision, flux, g, use_graph, elems_per_block, matrix_cores, fused)
         h = C.c_void_p()
         nbytes = C.c_size_t()
         st = self.lib.esdg_swe_init(len(instances), arr, C.byref(opt), C.byref(h), C.byref(nbytes))

@@ -63,10 +63,12 @@ struct InstDesc {
   double g, Href, dt, pad1;
   void *uh;            // [3][K][Np] modal state (eta = h + b - Href, hu, hv)
   void *du;            // [3][K][Np] LSRK register
-  void *ut[3];         // [4][K][Nh] entropy-projected h~, u~, v~, H~ - Href (two stage buffers + rhs scratch)
+  void *ut[3];         // entropy-projected h~, u~, v~, H~ - Href at the hybrid nodes, tile-blocked:
+                       // the tile of elements k0..k0+ne-1 holds [4][ne][Nh] from real k0*4*Nh
+                       // (two stage buffers + rhs scratch)
   void *nbx[3];        // [K][Nfq][4] the same four values at each face node's neighbour, written
                        // by the neighbour's projection (one per ut buffer)
-  const void *geo;     // [4][K][Nh] rxJ, sxJ, ryJ, syJ
+  const void *geo;     // rxJ, sxJ, ryJ, syJ at the hybrid nodes, tile-blocked like ut
   const void *wJq;     // [K][Nq] w_q J (diagnostics)
   const void *bq;      // [K][Nq] bathymetry at volume nodes (diagnostics)
   const void *stat;    // static data in tile order: the tile of elements k0..k0+ne-1 holds, from
@@ -102,7 +104,18 @@ struct StageArgs {
   double rk_a, rk_b;
   const void *ext_state;  // kProject: read this state instead of desc.uh (when non-null)
   void *ext_rhs;          // kRhs: write here
-  int32_t *flag;          // set nonzero when a non-physical value is seen
+  int32_t *flag;          // bit 0: a non-physical value was seen; bit 1: a neighbour wait timed out
+  // Multi-stage launch (progress != null; all workgroups co-resident): nstages kStage stages
+  // starting at global stage index stage0, buffers alternating from in_buf, coefficients
+  // rk_a5/rk_b5[stage mod 5].  Before a stage, a tile waits until every tile holding a face
+  // neighbour has completed the previous one; after it, it publishes its count.
+  int32_t *progress;      // [ntiles] stages completed by each tile (monotone over launches)
+  const int32_t *nbr_off; // [ntiles + 1] CSR offsets into nbr_idx
+  const int32_t *nbr_idx; // tiles (other than itself) holding a face neighbour of each tile
+  int32_t stage0, nstages;
+  int32_t spin_limit;     // polls of one neighbour count before the wait gives up
+  int32_t pad2;
+  double rk_a5[5], rk_b5[5];
 };
 
 struct DiagArgs {

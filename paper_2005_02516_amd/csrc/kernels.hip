@@ -184,10 +184,9 @@ template <int N> struct ColParts { static constexpr int value = 2; };
 // Subtracting the constant g Href is exact: the projection reproduces constants.
 template <typename real, int N, int CM>
 __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L, real *out,
-                                             real *nbx_out, int32_t *flag) {
+                                             real *nbx_out, int32_t *flag, bool coherent) {
   constexpr bool mfma = CM != kValu;
   constexpr int Np = dim_Np(N), Nq = dim_Nq(N), Nh = dim_Nh(N), Nfq = dim_Nfq(N);
-  const int K = d.K;
   const double g = d.g, Href = d.Href;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int nc = 3 * ne;                       // contraction columns: (field, element)
@@ -270,7 +269,6 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
       __syncthreads();
     }
   }
-  const size_t plane = size_t(K) * Nh;
   for (int i = tid; i < ne * Nh; i += nth) {
     const int e = i / Nh, n = i - e * Nh;
     real t0 = 0, t1 = 0, t2 = 0;
@@ -290,15 +288,31 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
     const double v1 = t0, v2 = t1, v3 = t2;
     const double dH = (v1 + 0.5 * (v2 * v2 + v3 * v3)) / g;
     const double h = Href + dH - double(L.bh[i]);
-    const size_t o = size_t(k0) * Nh + i;
-    out[0 * plane + o] = real(h);
-    out[1 * plane + o] = real(v2);
-    out[2 * plane + o] = real(v3);
-    out[3 * plane + o] = real(dH);
+    const size_t o = size_t(k0) * 4 * Nh + i;     // tile-blocked [4][ne][Nh]
+    out[o] = real(h);
+    out[ne * Nh + o] = real(v2);
+    out[2 * ne * Nh + o] = real(v3);
+    out[3 * ne * Nh + o] = real(dH);
     if (n >= Nq) {                 // face node: also fill the neighbour's face slot
-      typedef real real4 __attribute__((ext_vector_type(4)));
-      const real4 val = {real(h), real(v2), real(v3), real(dH)};
-      *reinterpret_cast<real4 *>(nbx_out + size_t(L.pp[e * Nfq + (n - Nq)]) * 4) = val;
+      real *slot = nbx_out + size_t(L.pp[e * Nfq + (n - Nq)]) * 4;
+      if (coherent) {
+        // multi-stage launches: device-coherent stores (the neighbour's workgroup may sit on
+        // another XCD, whose L2 does not see this one's)
+        const real val[4] = {real(h), real(v2), real(v3), real(dH)};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if constexpr (sizeof(real) == 8)
+            __hip_atomic_store(reinterpret_cast<unsigned long long *>(slot) + c, __double_as_longlong(double(val[c])),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          else
+            __hip_atomic_store(reinterpret_cast<unsigned *>(slot) + c, __float_as_uint(float(val[c])),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      } else {
+        typedef real real4 __attribute__((ext_vector_type(4)));
+        const real4 val = {real(h), real(v2), real(v3), real(dH)};
+        *reinterpret_cast<real4 *>(slot) = val;
+      }
     }
     bad |= bad_value(h, v2, v3);
   }
@@ -313,13 +327,15 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
 typedef __attribute__((address_space(1))) const void *gptr_t;
 typedef __attribute__((address_space(3))) void *lptr_t;
 
+template <int CPOL = 0>
 __device__ inline void async_copy_words(uint32_t *dst, const uint32_t *src, int nwords) {
   const int lane = threadIdx.x & 63, wave = wave_id(), nwaves = blockDim.x >> 6;
   for (int c = wave * 64; c < nwords; c += nwaves * 64) {
     if (c + lane < nwords)
-      __builtin_amdgcn_global_load_lds((gptr_t)(src + c + lane), (lptr_t)(dst + c), 4, 0, 0);
+      __builtin_amdgcn_global_load_lds((gptr_t)(src + c + lane), (lptr_t)(dst + c), 4, 0, CPOL);
   }
 }
+constexpr int kCpolAgent = 16;     // sc1: device-coherent access (other XCDs' stores visible)
 
 // 32-bit words of a tile's static block staged through registers during a stage.
 template <typename real>
@@ -331,19 +347,16 @@ __device__ __forceinline__ int stat_head(int nstat) {
 // Phase 0: fetch the tile's global data into LDS (all asynchronous; see above).
 template <typename real, int N>
 __device__ __forceinline__ void fetch_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, Lds<real, N> &L) {
-  constexpr int Np = dim_Np(N), Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
+  constexpr int Np = dim_Np(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
   constexpr int W = sizeof(real) / 4;     // 32-bit words per value
-  const size_t plane = size_t(d.K) * Nh, splane = size_t(d.K) * Np;
+  const size_t splane = size_t(d.K) * Np;
   auto words = [](const void *p) { return static_cast<const uint32_t *>(p); };
   auto lwords = [](real *p) { return reinterpret_cast<uint32_t *>(p); };
   if (a.mode != kProject) {
-    const real *ut = static_cast<const real *>(d.ut[a.in_buf]);
-    const real *geo = static_cast<const real *>(d.geo);
-    const size_t base = size_t(k0) * Nh;
-    for (int c = 0; c < 4; ++c) {
-      async_copy_words(lwords(L.raw + c * ne * Nh), words(ut + c * plane + base), ne * Nh * W);
-      async_copy_words(lwords(L.raw + (4 + c) * ne * Nh), words(geo + c * plane + base), ne * Nh * W);
-    }
+    // u~ and the metric factors are stored tile-blocked ([4][ne][Nh] per tile), one copy each
+    const size_t base = size_t(k0) * 4 * Nh;
+    async_copy_words(lwords(L.raw), words(static_cast<const real *>(d.ut[a.in_buf]) + base), 4 * ne * Nh * W);
+    async_copy_words(lwords(L.raw + 4 * ne * Nh), words(static_cast<const real *>(d.geo) + base), 4 * ne * Nh * W);
   }
   if (a.mode == kStage) {
     const real *uh = static_cast<const real *>(d.uh);
@@ -365,9 +378,13 @@ __device__ __forceinline__ void fetch_tile(const StageArgs &a, const InstDesc &d
     async_copy_words(lwords(L.Minv) + head, words(static_cast<const real *>(d.stat) + size_t(k0) * stat_words(N)) + head,
                      nstat - head);
   }
-  if (a.mode != kProject)          // neighbour values, pushed here by the neighbours' projections
-    async_copy_words(lwords(L.nb), words(static_cast<const real *>(d.nbx[a.in_buf]) + size_t(k0) * Nfq * 4),
-                     ne * Nfq * 4 * W);
+  if (a.mode != kProject) {        // neighbour values, pushed here by the neighbours' projections
+    const uint32_t *src = words(static_cast<const real *>(d.nbx[a.in_buf]) + size_t(k0) * Nfq * 4);
+    if (a.progress)                // multi-stage launch: written during this kernel, maybe on another XCD
+      async_copy_words<kCpolAgent>(lwords(L.nb), src, ne * Nfq * 4 * W);
+    else
+      async_copy_words(lwords(L.nb), src, ne * Nfq * 4 * W);
+  }
   __builtin_amdgcn_s_waitcnt(0);   // this wave's copies have landed in LDS
 }
 
@@ -385,7 +402,11 @@ __device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int 
   const real g = real(d.g);
   typedef real real4 __attribute__((ext_vector_type(4)));
   const real *rbase = L.rec + e * Nh * kNodeRec;
+  // Row m accumulates, over its columns n, c = Qx {hu} + Qy {hv} (a0), u_n c and v_n c (b1,
+  // b2), and dH_n Qx, dH_n Qy (q1, q2); the row factors are applied once at the end:
+  //   sum_n ({u} c + gh_m dH_n Qx) = u_m a0 + b1 + gh_m q1   (halves folded into the records)
   real hu[R], hv[R], u[R], v[R], gh[R], rx[R], sx[R], ry[R], sy[R], a0[R], a1[R], a2[R];
+  real b1[R], b2[R], q1[R], q2[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const real *rm = rbase + (m0 + r) * kNodeRec;
@@ -393,7 +414,7 @@ __device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int 
     hu[r] = s0.x; hv[r] = s0.y; u[r] = s0.z; v[r] = s0.w;
     rx[r] = s1.x; sx[r] = s1.y; ry[r] = s1.z; sy[r] = s1.w;
     gh[r] = rm[8];
-    a0[r] = 0; a1[r] = 0; a2[r] = 0;
+    a0[r] = 0; b1[r] = 0; b2[r] = 0; q1[r] = 0; q2[r] = 0;
   }
 #pragma unroll 2
   for (int n = n_lo; n < n_hi; ++n) {
@@ -408,11 +429,17 @@ __device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int 
       const real Qx = (rx[r] + rxn) * Sr + (sx[r] + sxn) * Ss;
       const real Qy = (ry[r] + ryn) * Sr + (sy[r] + syn) * Ss;
       const real c = Qx * (hu[r] + hun) + Qy * (hv[r] + hvn);
-      const real t = gh[r] * dHn;
       a0[r] += c;
-      a1[r] += (u[r] + un) * c + t * Qx;
-      a2[r] += (v[r] + vn) * c + t * Qy;
+      b1[r] += un * c;
+      b2[r] += vn * c;
+      q1[r] += dHn * Qx;
+      q2[r] += dHn * Qy;
     }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    a1[r] = u[r] * a0[r] + b1[r] + gh[r] * q1[r];
+    a2[r] = v[r] * a0[r] + b2[r] + gh[r] * q2[r];
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -500,7 +527,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
   if (a.mode == kProject) {
     __syncthreads();
     project_tile<real, N, CM>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]),
-                              static_cast<real *>(d.nbx[a.out_buf]), a.flag);
+                              static_cast<real *>(d.nbx[a.out_buf]), a.flag, a.progress != nullptr);
     return;
   }
   __syncthreads();
@@ -580,7 +607,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
   if (a.mode == kStage) {
     __syncthreads();
     project_tile<real, N, CM>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]),
-                              static_cast<real *>(d.nbx[a.out_buf]), a.flag);
+                              static_cast<real *>(d.nbx[a.out_buf]), a.flag, a.progress != nullptr);
   }
 }
 
@@ -596,11 +623,48 @@ __device__ __forceinline__ const T &read_const(const T *p, int i) {
   return *(const T *)((const __attribute__((address_space(4))) T *)p + i);
 }
 
+// Multi-stage launches: before stage `target` of tile t, wait until every tile holding a
+// face neighbour of t has published `target` completed stages (their projection has pushed
+// t's neighbour values, and they have finished reading the slots t is about to fill).
+// Wave 0 polls, one neighbour per lane, with device-coherent loads and a bounded spin; the
+// barrier then releases the other waves.  The neighbour values themselves are read with
+// device-coherent copies (fetch_tile), so no cache-wide invalidation is needed.  Returns
+// false (for the whole workgroup) if a wait gave up.
+__device__ __forceinline__ bool wait_neighbours(const StageArgs &a, int t, int target) {
+  int ok = 1;
+  if (threadIdx.x < 64) {
+    const int b = read_const(a.nbr_off, t), e = read_const(a.nbr_off, t + 1);
+    for (int j = b + int(threadIdx.x); j < e; j += 64) {
+      const int u = read_const(a.nbr_idx, j);
+      int spins = 0;
+      while (__hip_atomic_load(a.progress + u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++spins > a.spin_limit) { ok = 0; break; }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+  }
+  return __syncthreads_and(ok) != 0;
+}
+
+// After a stage of tile t: every wave waits until its stores have completed (the pushed
+// face values are device-coherent stores, so completion means visible to every XCD), then
+// one thread publishes the tile's completed-stage count.  The tile's other outputs are read
+// back only by this workgroup.
+__device__ __forceinline__ void publish(const StageArgs &a, int t, int value) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(a.progress + t, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Persistent stage kernel: block b walks a contiguous range of tiles.  Blocks are dealt
 // to the XCDs round-robin, so block b's range is chosen as range number
-// (b mod kXcds) * (gridDim / kXcds) + b / kXcds: each XCD owns a contiguous run of tiles
-// and face neighbours written by the previous stage tend to sit in its L2.  The
-// reference-operator block stays in LDS and is reloaded only when the degree changes.
+// (b mod kXcds) * (gridDim / kXcds) + b / kXcds: each XCD owns a contiguous run of tiles.
+// The reference-operator block stays in LDS and is reloaded only when the degree changes.
+// With a.progress set, the launch runs a.nstages RK stages: each block takes its tiles
+// through stage s before stage s + 1, and a tile starts a stage once its face neighbours'
+// tiles have finished the previous one (see wait_neighbours), which the co-residency of
+// all workgroups (cooperative launch) makes safe.  A wait that gives up sets flag bit 1
+// and ends the workgroup; its neighbours' waits then give up in turn.
 template <typename real, int CM>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel(StageArgs a) {
@@ -611,26 +675,43 @@ stage_kernel(StageArgs a) {
   const int chunk = (int(blockIdx.x) % kXcds) * (G / kXcds) + int(blockIdx.x) / kXcds;
   const int t0 = a.ranges ? read_const(a.ranges, chunk) : int((long long)chunk * a.ntiles / G);
   const int t1 = a.ranges ? read_const(a.ranges, chunk + 1) : int((long long)(chunk + 1) * a.ntiles / G);
+  const bool multi = a.progress != nullptr;
+  const int nst = multi ? a.nstages : 1;
   int loaded_N = 0;
-  for (int t = t0; t < t1; ++t) {
-    const Tile tl = read_const(a.tiles, t);
-    const InstDesc &d = read_const(a.desc, tl.inst);
-    if (d.N != loaded_N) {
-      __syncthreads();
-      const real *ref = static_cast<const real *>(d.ref);
-      const int words = ref_words(d.N);
-      for (int i = threadIdx.x; i < words; i += blockDim.x) sm[i] = ref[i];
-      loaded_N = d.N;
+  for (int s = 0; s < nst; ++s) {
+    StageArgs as = a;
+    if (multi) {
+      as.mode = kStage;
+      as.in_buf = (a.in_buf + s) & 1;
+      as.out_buf = 1 - as.in_buf;
+      as.rk_a = a.rk_a5[s % 5];
+      as.rk_b = a.rk_b5[s % 5];
     }
-    switch (d.N) {
-      case 1: stage_tile<real, 1, RowsPerThread<1>::value, CM>(a, d, tl.k0, tl.ne, sm, tile); break;
-      case 2: stage_tile<real, 2, RowsPerThread<2>::value, CM>(a, d, tl.k0, tl.ne, sm, tile); break;
-      case 3: stage_tile<real, 3, RowsPerThread<3>::value, CM>(a, d, tl.k0, tl.ne, sm, tile); break;
-      case 4: stage_tile<real, 4, RowsPerThread<4>::value, CM>(a, d, tl.k0, tl.ne, sm, tile); break;
-      case 5: stage_tile<real, 5, RowsPerThread<5>::value, CM>(a, d, tl.k0, tl.ne, sm, tile); break;
-      default: break;
+    for (int t = t0; t < t1; ++t) {
+      if (multi && s > 0 && !wait_neighbours(a, t, a.stage0 + s)) {
+        if (threadIdx.x == 0) atomicOr(a.flag, 2);
+        return;
+      }
+      const Tile tl = read_const(a.tiles, t);
+      const InstDesc &d = read_const(a.desc, tl.inst);
+      if (d.N != loaded_N) {
+        __syncthreads();
+        const real *ref = static_cast<const real *>(d.ref);
+        const int words = ref_words(d.N);
+        for (int i = threadIdx.x; i < words; i += blockDim.x) sm[i] = ref[i];
+        loaded_N = d.N;
+      }
+      switch (d.N) {
+        case 1: stage_tile<real, 1, RowsPerThread<1>::value, CM>(as, d, tl.k0, tl.ne, sm, tile); break;
+        case 2: stage_tile<real, 2, RowsPerThread<2>::value, CM>(as, d, tl.k0, tl.ne, sm, tile); break;
+        case 3: stage_tile<real, 3, RowsPerThread<3>::value, CM>(as, d, tl.k0, tl.ne, sm, tile); break;
+        case 4: stage_tile<real, 4, RowsPerThread<4>::value, CM>(as, d, tl.k0, tl.ne, sm, tile); break;
+        case 5: stage_tile<real, 5, RowsPerThread<5>::value, CM>(as, d, tl.k0, tl.ne, sm, tile); break;
+        default: break;
+      }
+      if (multi) publish(a, t, a.stage0 + s + 1);
+      else __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -754,6 +835,16 @@ hipError_t launch_stage(bool fp64, const StageArgs &a, int max_blocks, size_t ld
   else
     hipLaunchKernelGGL((stage_kernel<float, kValu>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
   return hipGetLastError();
+}
+
+// Multi-stage launch: every workgroup of the grid must be resident at once (tiles wait on
+// their neighbours' progress), which the cooperative launch guarantees or refuses.
+hipError_t launch_stage_fused(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream) {
+  if (a.ntiles <= 0) return hipSuccess;
+  const int grid = stage_grid(a.ntiles, max_blocks);
+  StageArgs arg = a;
+  void *params[] = {&arg};
+  return hipLaunchCooperativeKernel(stage_fn(fp64, a.contraction), dim3(grid), dim3(kBlock), params, lds_bytes, stream);
 }
 
 hipError_t launch_diag(bool fp64, const DiagArgs &a, hipStream_t stream) {

@@ -20,6 +20,7 @@
 namespace esdg {
 hipError_t set_stage_lds_limit(bool fp64, int cm, size_t lds_bytes);
 hipError_t launch_stage(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream);
+hipError_t launch_stage_fused(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream);
 hipError_t stage_max_blocks(bool fp64, int cm, size_t lds_bytes, int *out);
 int stage_grid(int ntiles, int max_blocks);
 hipError_t launch_diag(bool fp64, const DiagArgs &a, hipStream_t stream);
@@ -70,6 +71,10 @@ struct esdg_swe {
   std::vector<Offsets> off;
   std::map<int, size_t> ref_off;
   size_t tiles_off = 0, desc_off = 0, flag_off = 0, partial_off = 0, ranges_off = 0;
+  size_t progress_off = 0, nbr_off_off = 0, nbr_idx_off = 0;
+  std::vector<int32_t> nbr_off, nbr_idx;   // tiles holding a face neighbour of each tile (CSR)
+  long long stage_count = 0;       // global index of the next stage of a fused launch
+  bool fused = false;
   bool balanced = false;           // mixed degrees: cost-balanced tile ranges uploaded
   size_t ws_bytes = 0;
   std::map<int, int> epb;          // elements per workgroup per N
@@ -175,6 +180,13 @@ esdg_status check_flag(esdg_swe *s) {
   if (flag) {
     int32_t zero = 0;
     (void)hipMemcpy(s->dev<int32_t>(s->flag_off), &zero, sizeof zero, hipMemcpyHostToDevice);
+    if (flag & 2) {
+      // a fused launch gave up waiting: restart the stage counts from zero
+      std::vector<int32_t> z(s->tiles.size(), 0);
+      (void)hipMemcpy(s->dev<int32_t>(s->progress_off), z.data(), z.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+      s->stage_count = 0;
+      return s->fail(ESDG_EDEVICE, "fused step: a tile's wait for its neighbours gave up; the state is undefined");
+    }
     return s->fail(ESDG_ENONPHYS, "a kernel saw a non-finite value or a depth h~ <= 0");
   }
   return ESDG_OK;
@@ -298,6 +310,25 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
     for (int k0 = 0; k0 < inst[i].K; k0 += E) s->tiles.push_back(Tile{i, k0, std::min(E, inst[i].K - k0), 0});
     s->tile_count[i] = int(s->tiles.size()) - s->tile_begin[i];
   }
+  // tiles holding face neighbours of each tile (for fused multi-stage launches)
+  s->nbr_off.assign(1, 0);
+  for (int i = 0; i < n_inst; ++i) {
+    const InstanceHost &H = s->host[i];
+    const int Nh = dim_Nh(H.N), Nfq = dim_Nfq(H.N), E = s->epb[H.N];
+    for (int t = s->tile_begin[i]; t < s->tile_begin[i] + s->tile_count[i]; ++t) {
+      std::vector<int32_t> nb;
+      for (int k = s->tiles[t].k0; k < s->tiles[t].k0 + s->tiles[t].ne; ++k)
+        for (int f = 0; f < Nfq; ++f) {
+          const int u = s->tile_begin[i] + H.mapP[size_t(k) * Nfq + f] / Nh / E;
+          if (u != t) nb.push_back(u);
+        }
+      std::sort(nb.begin(), nb.end());
+      nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+      s->nbr_idx.insert(s->nbr_idx.end(), nb.begin(), nb.end());
+      s->nbr_off.push_back(int32_t(s->nbr_idx.size()));
+    }
+  }
+  s->fused = opt->fused_steps != 0;
   // workspace layout
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -326,6 +357,9 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
   s->flag_off = take(256);
   s->partial_off = take(s->tiles.size() * 6 * sizeof(double));
   s->ranges_off = take((s->tiles.size() + 16) * sizeof(int32_t));
+  s->progress_off = take(s->tiles.size() * sizeof(int32_t));
+  s->nbr_off_off = take(s->nbr_off.size() * sizeof(int32_t));
+  s->nbr_idx_off = take(std::max<size_t>(s->nbr_idx.size(), 1) * sizeof(int32_t));
   s->ws_bytes = o;
   s->desc.resize(n_inst);
   s->state_set.assign(n_inst, false);
@@ -365,8 +399,18 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
   for (int i = 0; i < s->n_inst; ++i) {
     const InstanceHost &H = s->host[i];
     const Offsets &f = s->off[i];
-    keep.push_back(to_bulk(H.geo, s->fp64));
-    if ((st = upload(s, f.geo, keep.back().data(), keep.back().size()))) return st;
+    {
+      // metric factors in tile-blocked order: [4][ne][Nh] per tile, from k0 * 4 * Nh
+      const size_t Nh = size_t(dim_Nh(H.N)), plane = size_t(H.K) * Nh;
+      std::vector<double> g(H.geo.size());
+      for (int t = s->tile_begin[i]; t < s->tile_begin[i] + s->tile_count[i]; ++t) {
+        const size_t k0 = size_t(s->tiles[t].k0), ne = size_t(s->tiles[t].ne);
+        for (size_t c = 0; c < 4; ++c)
+          for (size_t j = 0; j < ne * Nh; ++j) g[k0 * 4 * Nh + c * ne * Nh + j] = H.geo[c * plane + k0 * Nh + j];
+      }
+      keep.push_back(to_bulk(g, s->fp64));
+      if ((st = upload(s, f.geo, keep.back().data(), keep.back().size()))) return st;
+    }
     keep.push_back(to_bulk(H.wJq, s->fp64));
     if ((st = upload(s, f.wJq, keep.back().data(), keep.back().size()))) return st;
     keep.push_back(to_bulk(H.bq, s->fp64));
@@ -428,6 +472,19 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
   }
   if ((st = upload(s, s->desc_off, s->desc.data(), s->desc.size() * sizeof(InstDesc)))) return st;
   if ((st = upload(s, s->tiles_off, s->tiles.data(), s->tiles.size() * sizeof(Tile)))) return st;
+  if ((st = upload(s, s->nbr_off_off, s->nbr_off.data(), s->nbr_off.size() * sizeof(int32_t)))) return st;
+  if (!s->nbr_idx.empty() && (st = upload(s, s->nbr_idx_off, s->nbr_idx.data(), s->nbr_idx.size() * sizeof(int32_t))))
+    return st;
+  keep.push_back(std::vector<unsigned char>(s->tiles.size() * sizeof(int32_t), 0));
+  if ((st = upload(s, s->progress_off, keep.back().data(), keep.back().size()))) return st;
+  s->stage_count = 0;
+  if (s->fused) {
+    int dev = 0, coop = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+    if (e != hipSuccess) return s->hip_fail(e, "hipDeviceGetAttribute (cooperative launch)");
+    if (!coop) return s->fail(ESDG_EDEVICE, "fused_steps: the device does not support cooperative launches");
+  }
   // mixed degrees: split the tile list into contiguous chunks of equal estimated cost
   std::vector<int32_t> ranges;
   if (s->refs.size() > 1) {
@@ -542,6 +599,42 @@ static esdg_status run_steps_direct(esdg_swe *s, int nsteps) {
   return ESDG_OK;
 }
 
+// All 5 * nsteps stages in one cooperative launch (see stage_kernel).  Stage counts are
+// global and monotone; launches of at most 2^20 steps keep them well inside int32.
+static esdg_status run_steps_fused(esdg_swe *s, int nsteps) {
+  for (int done = 0; done < nsteps;) {
+    const int n = std::min(nsteps - done, 1 << 20);
+    if (s->stage_count + 5LL * n >= (1LL << 31) - 1) {
+      std::vector<int32_t> z(s->tiles.size(), 0);
+      hipError_t e = hipMemcpyAsync(s->dev<int32_t>(s->progress_off), z.data(), z.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, s->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+      if (e != hipSuccess) return s->hip_fail(e, "reset of the stage counts");
+      s->stage_count = 0;
+    }
+    StageArgs a = base_args(s, -1);
+    a.mode = kStage;
+    a.in_buf = s->parity;
+    a.out_buf = 1 - s->parity;
+    a.progress = s->dev<int32_t>(s->progress_off);
+    a.nbr_off = s->dev<int32_t>(s->nbr_off_off);
+    a.nbr_idx = s->dev<int32_t>(s->nbr_idx_off);
+    a.stage0 = int32_t(s->stage_count);
+    a.nstages = 5 * n;
+    a.spin_limit = 1 << 17;     // polls (each a device-coherent load): tens of ms, above any one stage
+    for (int st = 0; st < 5; ++st) {
+      a.rk_a5[st] = kRkA[st];
+      a.rk_b5[st] = kRkB[st];
+    }
+    hipError_t e = launch_stage_fused(s->fp64, a, s->max_blocks, s->lds_bytes, s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "hipLaunchCooperativeKernel (fused steps)");
+    s->stage_count += 5LL * n;
+    if (n & 1) s->parity = 1 - s->parity;
+    done += n;
+  }
+  return ESDG_OK;
+}
+
 esdg_status esdg_swe_step(esdg_swe *s, const double *dt, int32_t nsteps) {
   if (!s) return ESDG_EINVAL;
   if (!s->bound) return s->fail(ESDG_ESTATE, "step before bind");
@@ -561,6 +654,7 @@ esdg_status esdg_swe_step(esdg_swe *s, const double *dt, int32_t nsteps) {
     if (st) return st;
   }
   if (nsteps == 0) return ESDG_OK;
+  if (s->fused) return run_steps_fused(s, nsteps);
   if (!s->opt.use_graph || s->stream == nullptr) return run_steps_direct(s, nsteps);
   // graphs of an even number of steps keep the stage-buffer parity; replay them
   const int chunk = std::min(nsteps - nsteps % 2, 20);

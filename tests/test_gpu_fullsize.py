@@ -180,3 +180,17 @@ def test_config5_full_sampled_bf16x3(torch_mod):
     print(f"config5 bf16x3: worst err / (2^-16 bound) {worst:.3f}, max err / max|rhs| "
           f"{np.abs(r_gpu[:, ks] - r_ref).max() / np.abs(r_ref).max():.2e}", flush=True)
     assert ok, worst
+
+
+def test_config2_fused_steps_bitwise(torch_mod):
+    """Config 2 at full size, 20 steps in one fused launch against per-stage graph replays."""
+    from paper_2005_02516_amd.binding import EsdgSwe
+    w = wl.config2()
+    out = []
+    for fused in (False, True):
+        s = EsdgSwe([w], precision="fp32", flux=w.flux, g=w.g, fused=fused)
+        s.set_state(0, w.u_nodes)
+        s.step(w.dt, 20)
+        out.append(s.get_state(0))
+        s.close()
+    assert np.array_equal(out[0], out[1])

@@ -336,3 +336,41 @@ def test_steps_fp64_matrix_cores(torch):
     u_ref, _ = O.run(o, uh0, w.dt, 10)
     err = rel_l2(u, u_ref, norm_by=np.linalg.norm(u_ref[0]))
     assert np.all(err < 1e-12), err
+
+
+def _run_steps(ws, precision, nsteps, **kw):
+    s = solver(ws, precision, "lf", **kw)
+    for i, w in enumerate(ws):
+        s.set_state(i, w.u_nodes)
+    s.step(np.array([w.dt for w in ws]), nsteps)
+    out = [s.get_state(i) for i in range(len(ws))]
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_fused_steps_bitwise(torch, precision):
+    """All RK stages of a step call in one cooperative launch (tiles wait on their face
+    neighbours' progress instead of a kernel boundary): bitwise the per-stage result."""
+    w = wl.config2(n=8, N=3)
+    ref = _run_steps([w], precision, 7, fused=False)
+    got = _run_steps([w], precision, 7, fused=True)
+    assert np.array_equal(ref[0], got[0])
+
+
+def test_fused_steps_many_tiles_per_block(torch):
+    """More tiles than resident workgroups (2 elements per tile on K = 32768): each workgroup
+    walks several tiles per stage, some of them neighbours of each other."""
+    w = wl.config2(n=128, N=3)
+    ref = _run_steps([w], "fp32", 3, fused=False, elems_per_block=2)
+    got = _run_steps([w], "fp32", 3, fused=True, elems_per_block=2)
+    assert np.array_equal(ref[0], got[0])
+
+
+def test_fused_steps_mixed_ensemble(torch):
+    """Mixed degrees (cost-balanced tile ranges) in one fused launch: bitwise per instance."""
+    ws = wl.config4_instances(count=4, n_override=[3, 4, 2, 5], N_override=[2, 3, 4, 3])
+    ref = _run_steps(ws, "fp32", 4, fused=False)
+    got = _run_steps(ws, "fp32", 4, fused=True)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
