@@ -105,12 +105,16 @@ typedef struct {
   int32_t matrix_cores;     /* projection/lift contractions with constant operators: 0 or 1 =
                                vector ALUs, 2 = matrix cores (MFMA) in the bulk precision;
                                ESDG_FP32_BF16X3 always uses the split-bf16 matrix-core path  */
-  int32_t fused_steps;      /* nonzero: esdg_swe_step runs all its RK stages in one
-                               cooperative launch, each element tile starting a stage once
+  int32_t fused_steps;      /* how esdg_swe_step launches its RK stages: 0 = one launch per
+                               stage (HIP graphs if use_graph); 1 = all stages of the call in
+                               one cooperative launch, each element tile starting a stage once
                                the tiles of its face neighbours have finished the previous
-                               one (no grid-wide barrier; use_graph is then ignored).  Bind
-                               fails with ESDG_EDEVICE where cooperative launch is missing.
-                               Results are bitwise those of the per-stage launches.           */
+                               one (no grid-wide barrier); when every workgroup holds at most
+                               one tile, that tile also stays in LDS from the first stage to
+                               the last; 2 = automatic: 1 when every workgroup holds at most
+                               one tile, else 0.  With 1 (or 2 resolving to 1) bind fails with
+                               ESDG_EDEVICE where cooperative launch is missing.  Results are
+                               bitwise the same in every mode.                                */
 } esdg_swe_options;
 
 /* Plan a solver for n_inst independent instances (n_inst = 1 for a single run).  Builds,
@@ -179,6 +183,12 @@ esdg_status esdg_swe_reference_level(const esdg_swe *s, int32_t inst, double *Hr
 
 /* Sizes of instance `inst`: out = {N, K, Np, Nq, Nfq, Nh}. */
 esdg_status esdg_swe_query(const esdg_swe *s, int32_t inst, int32_t *out6);
+
+/* Launch plan (after bind): out = {element tiles, resident workgroups of the stage kernel,
+ * LDS bytes per workgroup, step mode (0 = one launch per stage, 1 = one launch per step
+ * call re-reading tiles every stage, 2 = one launch per step call with tiles resident in
+ * LDS)}.  ESDG_ESTATE before bind. */
+esdg_status esdg_swe_launch_info(const esdg_swe *s, int32_t *out4);
 
 /* Message for the last failing call on s (s may be NULL: last failing init on this thread). */
 const char *esdg_swe_last_error(const esdg_swe *s);

@@ -24,7 +24,7 @@ FLUXES = {"ec": ESDG_FLUX_EC, "lf": ESDG_FLUX_LF}
 EXPORTED = [
     "esdg_swe_init", "esdg_swe_bind", "esdg_swe_set_state", "esdg_swe_set_state_modal", "esdg_swe_get_state",
     "esdg_swe_state_device", "esdg_swe_rhs", "esdg_swe_step", "esdg_swe_diagnostics", "esdg_swe_sync",
-    "esdg_swe_query", "esdg_swe_reference_level", "esdg_swe_last_error", "esdg_swe_destroy",
+    "esdg_swe_query", "esdg_swe_launch_info", "esdg_swe_reference_level", "esdg_swe_last_error", "esdg_swe_destroy",
 ]
 
 
@@ -39,8 +39,11 @@ class esdg_swe_options(C.Structure):
                 ("fused_steps", C.c_int32)]
 
 
+FUSED = {False: 0, True: 1, "auto": 2}
+
+
 def make_options(precision: str, flux: str, g: float, use_graph: bool = True, epb=None,
-                 matrix_cores: bool = False, fused: bool = False) -> esdg_swe_options:
+                 matrix_cores: bool = False, fused="auto") -> esdg_swe_options:
     """epb: None, an int (all degrees) or a mapping N -> elements per workgroup."""
     arr = (C.c_int32 * 6)()
     if isinstance(epb, int):
@@ -50,7 +53,7 @@ def make_options(precision: str, flux: str, g: float, use_graph: bool = True, ep
         for N, E in epb.items():
             arr[int(N)] = int(E)
     return esdg_swe_options(PRECISIONS[precision], FLUXES[flux], float(g), int(use_graph), arr,
-                            2 if matrix_cores else 1, 1 if fused else 0)
+                            2 if matrix_cores else 1, FUSED[fused])
 
 
 class EsdgError(RuntimeError):
@@ -130,10 +133,9 @@ class EsdgSwe:
             elems_per_block = lookup(precision, [(w.N, w.K) for w in instances])
         if matrix_cores is None:
             matrix_cores = os.environ.get("ESDG_SWE_MATRIX_CORES", "0") == "1"
-        if fused is None:
-            fused = os.environ.get("ESDG_SWE_FUSED", "0") == "1"
+        if fused is None:       # one launch per step call when tiles can stay resident
+            fused = {"0": False, "1": True}.get(os.environ.get("ESDG_SWE_FUSED", ""), "auto")
         self.elems_per_block = elems_per_block
-        self.fused = bool(fused)
         opt = make_options(precision, flux, g, use_graph, elems_per_block, matrix_cores, fused)
         h = C.c_void_p()
         nbytes = C.c_size_t()
@@ -155,6 +157,11 @@ class EsdgSwe:
     def _check(self, st: int):
         if st != ESDG_OK:
             raise EsdgError(st, self.lib.esdg_swe_last_error(self.h).decode())
+
+    def launch_info(self):
+        out = (C.c_int32 * 4)()
+        self._check(self.lib.esdg_swe_launch_info(self.h, out))
+        return dict(zip(["tiles", "resident_workgroups", "lds_bytes", "step_mode"], list(out)))
 
     def query(self, inst: int):
         out = (C.c_int32 * 6)()

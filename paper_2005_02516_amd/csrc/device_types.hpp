@@ -114,7 +114,8 @@ struct StageArgs {
   const int32_t *nbr_idx; // tiles (other than itself) holding a face neighbour of each tile
   int32_t stage0, nstages;
   int32_t spin_limit;     // polls of one neighbour count before the wait gives up
-  int32_t pad2;
+  int32_t resident;       // multi-stage launch with at most one tile per workgroup: the tile
+                          // stays in LDS from its first stage to its last (see stage_tile)
   double rk_a5[5], rk_b5[5];
 };
 

@@ -138,7 +138,7 @@ struct Lds {
   static constexpr int Np = dim_Np(N), Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
   real *ref, *Vh, *ST, *FT, *wf, *nr, *ns;
   real *rec, *raw, *nb, *U, *DU, *Minv, *wJ, *bq, *bh;
-  real *R, *T, *Q;
+  real *R, *T, *Q, *VH;
   int32_t *pp;
   // sm: the ref block (already loaded); tile: the tile region (after the largest ref block)
   __device__ Lds(real *sm, real *tile, int E) {
@@ -159,11 +159,13 @@ struct Lds {
     bq = wJ + E * Nq;
     bh = bq + E * Nq;
     pp = reinterpret_cast<int32_t *>(bh + E * Nh);
-    // reuse: residual and lift temporaries live in the raw block (dead after phase 1),
-    // the projection's pointwise values in the record block (dead after phase 2)
+    // reuse: the residual, lift and projection temporaries live in the raw block (dead
+    // after phase 1) and v'_h in the neighbour block (dead after the residual); the
+    // node records and the state are left alone, so a resident tile keeps them
     R = raw;                      // up to two partial residuals [2][3][E][Nh]
-    T = raw + 6 * E * Nh;
-    Q = rec;
+    T = raw + 6 * E * Nh;         // [3][E][Np]
+    Q = raw;                      // [3][E][Nq] projection's weighted entropy variables
+    VH = nb;                      // [3][E][Np] v'_h (3 Np <= 4 Nfq for N <= 5)
   }
 };
 
@@ -176,15 +178,24 @@ template <> struct RowsPerThread<5> { static constexpr int value = 1; };
 // Column parts of the residual phase, per degree (1 or 2).
 template <int N> struct ColParts { static constexpr int value = 2; };
 
+// Stage flags of a multi-stage launch whose tiles stay in LDS (StageArgs::resident).
+constexpr int kResident = 1;       // the tile's records, metric factors, static block, state and
+                                   // RK register stay in LDS between the stages of the launch
+constexpr int kResMid = 2;         // not the first stage: only the neighbour values are fetched
+constexpr int kResLast = 4;        // last stage: the state, RK register and u~ go to HBM
+
 // Entropy projection of the tile states in L.U ([3][ne][Np]: eta, hu, hv) to the
-// hybridized nodes (Section 2.6), written to out ([4][K][Nh]: h~, u~, v~, H~ - Href):
+// hybridized nodes (Section 2.6), written to out (tile-blocked [4][ne][Nh]: h~, u~, v~,
+// H~ - Href) or, in a resident stage that is not the last, straight into the node records
+// of the next stage (the same values the records phase would form from out):
 //   q = V_q u_h; h = eta_q + Href - b_q; v' = (g eta_q - |u|^2/2, u, v) = v(u_q) - (g Href, 0, 0)
 //   (FP64); v'_h = Minv_k V_q^T diag(w J) v'_q; v~' = V_h v'_h;
 //   H~ - Href = (v~1' + |v~23|^2/2)/g, h~ = Href + (H~ - Href) - b~ (FP64).
 // Subtracting the constant g Href is exact: the projection reproduces constants.
 template <typename real, int N, int CM>
 __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L, real *out,
-                                             real *nbx_out, int32_t *flag, bool coherent) {
+                                             real *nbx_out, int32_t *flag, bool coherent, int res = 0) {
+  const bool to_records = (res & kResident) && !(res & kResLast);
   constexpr bool mfma = CM != kValu;
   constexpr int Np = dim_Np(N), Nq = dim_Nq(N), Nh = dim_Nh(N), Nfq = dim_Nfq(N);
   const double g = d.g, Href = d.Href;
@@ -258,13 +269,13 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
       vb += Mi[j + 1] * Tc[j + 1];
     }
     if (Np & 1) va += Mi[Np - 1] * Tc[Np - 1];
-    L.U[i] = va + vb;
+    L.VH[i] = va + vb;
   }
   __syncthreads();
   if constexpr (CM != kValu) {
     {                              // v~ = V_h v_h on the matrix cores
       gemm_mfma<CM, real>(Nh, Np, nc, [&](int i, int k) { return L.Vh[i * Np + k]; },
-                  [&](int k, int c) { return L.U[c * Np + k]; },
+                  [&](int k, int c) { return L.VH[c * Np + k]; },
                   [&](int i, int c, real v) { Stage[c * Nh + i] = v; });
       __syncthreads();
     }
@@ -280,19 +291,27 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
 #pragma unroll 4
       for (int j = 0; j < Np; ++j) {
         const real v = L.Vh[n * Np + j];
-        t0 += v * L.U[0 * ne * Np + e * Np + j];
-        t1 += v * L.U[1 * ne * Np + e * Np + j];
-        t2 += v * L.U[2 * ne * Np + e * Np + j];
+        t0 += v * L.VH[0 * ne * Np + e * Np + j];
+        t1 += v * L.VH[1 * ne * Np + e * Np + j];
+        t2 += v * L.VH[2 * ne * Np + e * Np + j];
       }
     }
     const double v1 = t0, v2 = t1, v3 = t2;
     const double dH = (v1 + 0.5 * (v2 * v2 + v3 * v3)) / g;
     const double h = Href + dH - double(L.bh[i]);
-    const size_t o = size_t(k0) * 4 * Nh + i;     // tile-blocked [4][ne][Nh]
-    out[o] = real(h);
-    out[ne * Nh + o] = real(v2);
-    out[2 * ne * Nh + o] = real(v3);
-    out[3 * ne * Nh + o] = real(dH);
+    if (to_records) {
+      typedef real real4 __attribute__((ext_vector_type(4)));
+      const real hr = real(h), ur = real(v2), vr = real(v3), gr = real(d.g);
+      real4 *rec = reinterpret_cast<real4 *>(L.rec + i * kNodeRec);
+      rec[0] = real4{real(0.5) * hr * ur, real(0.5) * hr * vr, real(0.5) * ur, real(0.5) * vr};
+      rec[2] = real4{real(0.5) * gr * hr, real(dH), hr, real(0)};
+    } else {
+      const size_t o = size_t(k0) * 4 * Nh + i;   // tile-blocked [4][ne][Nh]
+      out[o] = real(h);
+      out[ne * Nh + o] = real(v2);
+      out[2 * ne * Nh + o] = real(v3);
+      out[3 * ne * Nh + o] = real(dH);
+    }
     if (n >= Nq) {                 // face node: also fill the neighbour's face slot
       real *slot = nbx_out + size_t(L.pp[e * Nfq + (n - Nq)]) * 4;
       if (coherent) {
@@ -504,12 +523,23 @@ __device__ __forceinline__ void residual_tile(const InstDesc &d, int ne, Lds<rea
 }
 
 template <typename real, int N, int R, int CM>
-__device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm, real *tile) {
-  constexpr int Np = dim_Np(N), Nh = dim_Nh(N);
+__device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm, real *tile,
+                                           int res = 0) {
+  constexpr int Np = dim_Np(N), Nh = dim_Nh(N), Nfq = dim_Nfq(N);
   const int tid = threadIdx.x, nth = blockDim.x;
   Lds<real, N> L(sm, tile, ne);
   const real g = real(d.g);
-  fetch_tile<real, N>(a, d, k0, ne, L);
+  const bool mid = res & kResMid;                // resident tile after its first stage
+  const bool keep = (res & kResident) && !(res & kResLast);   // state stays in LDS only
+  if (mid) {
+    // everything but the neighbour values is still in LDS from the previous stage
+    async_copy_words<kCpolAgent>(reinterpret_cast<uint32_t *>(L.nb),
+                                 static_cast<const uint32_t *>(d.nbx[a.in_buf]) + size_t(k0) * Nfq * 4 * (sizeof(real) / 4),
+                                 ne * Nfq * 4 * int(sizeof(real) / 4));
+    __builtin_amdgcn_s_waitcnt(0);
+  } else {
+    fetch_tile<real, N>(a, d, k0, ne, L);
+  }
   // head of the static block: loaded into registers now, while the node records and the
   // residual run, and written to LDS before the barrier that ends the residual
   constexpr int W = sizeof(real) / 4;
@@ -517,7 +547,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
   constexpr int SR = StatRegs<real>::value;
   const uint32_t *sg = static_cast<const uint32_t *>(d.stat) + size_t(k0) * stat_words(N) * W;
   uint32_t sreg[SR];
-  if (a.mode != kProject) {
+  if (a.mode != kProject && !mid) {
 #pragma unroll
     for (int j = 0; j < SR; ++j) {
       const int v = tid + j * kBlock;
@@ -531,8 +561,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
     return;
   }
   __syncthreads();
-  // phase 1: node records from the fetched u~ and metric factors
-  for (int i = tid; i < ne * Nh; i += nth) {
+  // phase 1: node records from the fetched u~ and metric factors (a resident tile's
+  // previous projection wrote them directly)
+  for (int i = tid; i < ne * Nh && !mid; i += nth) {
     const real h = L.raw[i], u = L.raw[ne * Nh + i], v = L.raw[2 * ne * Nh + i], dH = L.raw[3 * ne * Nh + i];
     typedef real real4 __attribute__((ext_vector_type(4)));
     real4 *rec = reinterpret_cast<real4 *>(L.rec + i * kNodeRec);
@@ -542,7 +573,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
   }
   __syncthreads();
   residual_tile<real, N, R, ColParts<N>::value>(d, ne, L);
-  {
+  if (!mid) {
     uint32_t *sl = reinterpret_cast<uint32_t *>(L.Minv);
 #pragma unroll
     for (int j = 0; j < SR; ++j) {
@@ -599,15 +630,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
     } else {
       const real dn = ra * L.DU[i] + rdt * rr;
       const real un = L.U[i] + rb * dn;
-      du[o] = dn;
-      uh[o] = un;
+      if (!keep) {
+        du[o] = dn;
+        uh[o] = un;
+      }
+      L.DU[i] = dn;
       L.U[i] = un;
     }
   }
   if (a.mode == kStage) {
     __syncthreads();
     project_tile<real, N, CM>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]),
-                              static_cast<real *>(d.nbx[a.out_buf]), a.flag, a.progress != nullptr);
+                              static_cast<real *>(d.nbx[a.out_buf]), a.flag, a.progress != nullptr, res);
   }
 }
 
@@ -676,6 +710,9 @@ stage_kernel(StageArgs a) {
   const int t0 = a.ranges ? read_const(a.ranges, chunk) : int((long long)chunk * a.ntiles / G);
   const int t1 = a.ranges ? read_const(a.ranges, chunk + 1) : int((long long)(chunk + 1) * a.ntiles / G);
   const bool multi = a.progress != nullptr;
+  // resident: the launch gives this workgroup at most one tile (cost-balanced ranges can
+  // still give a workgroup two; that one then re-reads its tiles every stage)
+  const bool resident = multi && a.resident && t1 - t0 <= 1;
   const int nst = multi ? a.nstages : 1;
   int loaded_N = 0;
   for (int s = 0; s < nst; ++s) {
@@ -694,6 +731,7 @@ stage_kernel(StageArgs a) {
       }
       const Tile tl = read_const(a.tiles, t);
       const InstDesc &d = read_const(a.desc, tl.inst);
+      const int res = resident ? kResident | (s > 0 ? kResMid : 0) | (s == nst - 1 ? kResLast : 0) : 0;
       if (d.N != loaded_N) {
         __syncthreads();
         const real *ref = static_cast<const real *>(d.ref);
@@ -702,11 +740,11 @@ stage_kernel(StageArgs a) {
         loaded_N = d.N;
       }
       switch (d.N) {
-        case 1: stage_tile<real, 1, RowsPerThread<1>::value, CM>(as, d, tl.k0, tl.ne, sm, tile); break;
-        case 2: stage_tile<real, 2, RowsPerThread<2>::value, CM>(as, d, tl.k0, tl.ne, sm, tile); break;
-        case 3: stage_tile<real, 3, RowsPerThread<3>::value, CM>(as, d, tl.k0, tl.ne, sm, tile); break;
-        case 4: stage_tile<real, 4, RowsPerThread<4>::value, CM>(as, d, tl.k0, tl.ne, sm, tile); break;
-        case 5: stage_tile<real, 5, RowsPerThread<5>::value, CM>(as, d, tl.k0, tl.ne, sm, tile); break;
+        case 1: stage_tile<real, 1, RowsPerThread<1>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res); break;
+        case 2: stage_tile<real, 2, RowsPerThread<2>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res); break;
+        case 3: stage_tile<real, 3, RowsPerThread<3>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res); break;
+        case 4: stage_tile<real, 4, RowsPerThread<4>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res); break;
+        case 5: stage_tile<real, 5, RowsPerThread<5>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res); break;
         default: break;
       }
       if (multi) publish(a, t, a.stage0 + s + 1);

@@ -244,7 +244,8 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
   }
   *out = nullptr;
   if (opt->precision < ESDG_FP64 || opt->precision > ESDG_FP32_BF16X3 || opt->flux < 0 || opt->flux > 1 ||
-      !(opt->g > 0.0) || opt->matrix_cores < 0 || opt->matrix_cores > 2) {
+      !(opt->g > 0.0) || opt->matrix_cores < 0 || opt->matrix_cores > 2 || opt->fused_steps < 0 ||
+      opt->fused_steps > 2) {
     g_init_error = "esdg_swe_init: option out of range";
     return ESDG_EINVAL;
   }
@@ -328,7 +329,7 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
       s->nbr_off.push_back(int32_t(s->nbr_idx.size()));
     }
   }
-  s->fused = opt->fused_steps != 0;
+  s->fused = opt->fused_steps != 0;   // mode 2 is resolved at bind, once the resident count is known
   // workspace layout
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -478,12 +479,15 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
   keep.push_back(std::vector<unsigned char>(s->tiles.size() * sizeof(int32_t), 0));
   if ((st = upload(s, s->progress_off, keep.back().data(), keep.back().size()))) return st;
   s->stage_count = 0;
+  if (s->opt.fused_steps == 2)
+    s->fused = stage_grid(int(s->tiles.size()), s->max_blocks) >= int(s->tiles.size());
   if (s->fused) {
     int dev = 0, coop = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
     if (e != hipSuccess) return s->hip_fail(e, "hipDeviceGetAttribute (cooperative launch)");
-    if (!coop) return s->fail(ESDG_EDEVICE, "fused_steps: the device does not support cooperative launches");
+    if (!coop && s->opt.fused_steps == 2) s->fused = false;   // automatic: fall back to per-stage launches
+    else if (!coop) return s->fail(ESDG_EDEVICE, "fused_steps: the device does not support cooperative launches");
   }
   // mixed degrees: split the tile list into contiguous chunks of equal estimated cost
   std::vector<int32_t> ranges;
@@ -621,6 +625,7 @@ static esdg_status run_steps_fused(esdg_swe *s, int nsteps) {
     a.nbr_idx = s->dev<int32_t>(s->nbr_idx_off);
     a.stage0 = int32_t(s->stage_count);
     a.nstages = 5 * n;
+    a.resident = stage_grid(a.ntiles, s->max_blocks) >= a.ntiles ? 1 : 0;   // one tile per workgroup
     a.spin_limit = 1 << 17;     // polls (each a device-coherent load): tens of ms, above any one stage
     for (int st = 0; st < 5; ++st) {
       a.rk_a5[st] = kRkA[st];
@@ -732,6 +737,17 @@ esdg_status esdg_swe_query(const esdg_swe *s, int32_t inst, int32_t *out6) {
   out6[3] = dim_Nq(N);
   out6[4] = dim_Nfq(N);
   out6[5] = dim_Nh(N);
+  return ESDG_OK;
+}
+
+esdg_status esdg_swe_launch_info(const esdg_swe *s, int32_t *out4) {
+  if (!s || !out4) return ESDG_EINVAL;
+  if (!s->bound) return ESDG_ESTATE;
+  const int ntiles = int(s->tiles.size());
+  out4[0] = ntiles;
+  out4[1] = s->max_blocks;
+  out4[2] = int32_t(s->lds_bytes);
+  out4[3] = !s->fused ? 0 : (stage_grid(ntiles, s->max_blocks) >= ntiles ? 2 : 1);
   return ESDG_OK;
 }
 

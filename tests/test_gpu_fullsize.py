@@ -145,7 +145,7 @@ def test_graph_replay_matches_direct_fp32(torch_mod):
     w = wl.config2(n=32)
     out = []
     for g in (True, False):
-        s = EsdgSwe([w], precision="fp32", flux="lf", g=w.g, use_graph=g)
+        s = EsdgSwe([w], precision="fp32", flux="lf", g=w.g, use_graph=g, fused=False)
         s.set_state(0, w.u_nodes)
         for _ in range(3):
             s.step(w.dt, 4)

@@ -130,7 +130,7 @@ def test_steps_fp64_graph_and_direct(torch):
     d, o = oracle_for(w, "lf")
     res = {}
     for use_graph in (True, False):
-        s = solver(w, "fp64", "lf", use_graph=use_graph)
+        s = solver(w, "fp64", "lf", use_graph=use_graph, fused=False)
         s.set_state(0, w.u_nodes)
         uh0 = s.get_state(0)
         s.step(w.dt, 6)
