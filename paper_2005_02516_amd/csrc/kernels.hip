@@ -41,6 +41,15 @@ __device__ inline bool bad_value(double h, double a, double b) {
 // wave-sized chunks then keep their counters, bounds and LDS bases in scalar registers.
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6); }
 
+// The thread index, read through an empty asm so that the compiler cannot hoist index
+// arithmetic derived from it out of the stage loop of a multi-stage launch (hoisted, every
+// phase's per-thread indices would stay live across all phases and spill).
+__device__ __forceinline__ int phase_tid() {
+  int t = int(threadIdx.x);
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // ---------------------------------------------------------------- matrix-core contractions
 // C[M x NC] = A[M x KD] B[KD x NC], A and B read from LDS, on the matrix cores.  One wave
 // per 16x16 output block; blocks are dealt to the workgroup's waves.  Lane layout of the
@@ -169,11 +178,12 @@ struct Lds {
   }
 };
 
-// Rows per thread in the residual phase, per degree (must divide Nq and Nfq).
-template <int N> struct RowsPerThread { static constexpr int value = 1; };
-template <> struct RowsPerThread<1> { static constexpr int value = 2; };
-template <> struct RowsPerThread<3> { static constexpr int value = 2; };
-template <> struct RowsPerThread<5> { static constexpr int value = 1; };
+// Rows per thread in the residual phase, per degree (must divide Nq and Nfq).  Double tiles
+// take one row per task: two rows of double accumulators exceed the register budget of four
+// waves per SIMD and spill.
+template <typename real, int N> struct RowsPerThread { static constexpr int value = 1; };
+template <> struct RowsPerThread<float, 1> { static constexpr int value = 2; };
+template <> struct RowsPerThread<float, 3> { static constexpr int value = 2; };
 
 // Column parts of the residual phase, per degree (1 or 2).
 template <int N> struct ColParts { static constexpr int value = 2; };
@@ -199,7 +209,7 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
   constexpr bool mfma = CM != kValu;
   constexpr int Np = dim_Np(N), Nq = dim_Nq(N), Nh = dim_Nh(N), Nfq = dim_Nfq(N);
   const double g = d.g, Href = d.Href;
-  const int tid = threadIdx.x, nth = blockDim.x;
+  const int tid = phase_tid(), nth = blockDim.x;
   const int nc = 3 * ne;                       // contraction columns: (field, element)
   real *Stage = L.R;                           // [3][ne][Nq] or [3][ne][Nh] staging (free here)
   bool bad = false;
@@ -315,17 +325,18 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
     if (n >= Nq) {                 // face node: also fill the neighbour's face slot
       real *slot = nbx_out + size_t(L.pp[e * Nfq + (n - Nq)]) * 4;
       if (coherent) {
-        // multi-stage launches: device-coherent stores (the neighbour's workgroup may sit on
-        // another XCD, whose L2 does not see this one's)
-        const real val[4] = {real(h), real(v2), real(v3), real(dH)};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          if constexpr (sizeof(real) == 8)
-            __hip_atomic_store(reinterpret_cast<unsigned long long *>(slot) + c, __double_as_longlong(double(val[c])),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          else
-            __hip_atomic_store(reinterpret_cast<unsigned *>(slot) + c, __float_as_uint(float(val[c])),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // multi-stage launches: device-coherent (sc1) 16-byte vector stores, since the
+        // neighbour's workgroup may sit on another XCD, whose L2 does not see this one's.
+        // The slot is 16-byte aligned; publish() waits for these stores (vmcnt) itself.
+        if constexpr (sizeof(real) == 4) {
+          typedef float f4 __attribute__((ext_vector_type(4)));
+          const f4 val = {float(h), float(v2), float(v3), float(dH)};
+          asm volatile("global_store_dwordx4 %0, %1, off sc1" ::"v"(slot), "v"(val) : "memory");
+        } else {
+          typedef double d2 __attribute__((ext_vector_type(2)));
+          const d2 lo = {h, v2}, hi = {v3, dH};
+          asm volatile("global_store_dwordx4 %0, %1, off sc1" ::"v"(slot), "v"(lo) : "memory");
+          asm volatile("global_store_dwordx4 %0, %1, off sc1" ::"v"(slot + 2), "v"(hi) : "memory");
         }
       } else {
         typedef real real4 __attribute__((ext_vector_type(4)));
@@ -407,8 +418,42 @@ __device__ __forceinline__ void fetch_tile(const StageArgs &a, const InstDesc &d
   __builtin_amdgcn_s_waitcnt(0);   // this wave's copies have landed in LDS
 }
 
+// Interface terms of face node f (Section 2.8) from its node record rm and the neighbour's
+// values nbp (h, u, v, H - Href): W_f [ nJ . f_S(u~, u~+) + 1/2 g h (H+ - Href) nJ ] minus,
+// for the LF flux, the penalty 1/2 lambda sJ (u~+ - u~).  One function for the pair loop's
+// face rows and the separate interface pass, so both produce the same bits.
+template <typename real>
+__device__ __forceinline__ void interface_terms(const real *rm, const real *nbp, real wf, real nrf, real nsf, real g,
+                                                int flux, real &t0, real &t1, real &t2) {
+  typedef real real4 __attribute__((ext_vector_type(4)));
+  const real4 s0 = *reinterpret_cast<const real4 *>(rm), s1 = *reinterpret_cast<const real4 *>(rm + 4);
+  const real gh = rm[8], dH = rm[9], h = rm[10];
+  const real nJx = s1.x * nrf + s1.y * nsf, nJy = s1.z * nrf + s1.w * nsf;
+  const real uu = real(2) * s0.z, vv = real(2) * s0.w, huu = real(2) * s0.x, hvv = real(2) * s0.y;
+  const real hP = nbp[0], uP = nbp[1], vP = nbp[2], dHP = nbp[3];
+  const real huP = hP * uP, hvP = hP * vP;
+  const real hua = real(0.5) * (huu + huP), hva = real(0.5) * (hvv + hvP);
+  const real ua = real(0.5) * (uu + uP), va = real(0.5) * (vv + vP);
+  const real pr = gh * dHP;
+  real f0v = nJx * hua + nJy * hva;
+  real f1v = nJx * (hua * ua + pr) + nJy * hva * ua;
+  real f2v = nJx * hua * va + nJy * (hva * va + pr);
+  if (flux == 1) {
+    const real sJ = sqrt(nJx * nJx + nJy * nJy);
+    const real lm = fabs(uu * nJx + vv * nJy) + sqrt(g * h) * sJ;
+    const real lp = fabs(uP * nJx + vP * nJy) + sqrt(g * hP) * sJ;
+    const real c = real(0.5) * fmax(lm, lp);
+    f0v -= c * (dHP - dH);
+    f1v -= c * (huP - huu);
+    f2v -= c * (hvP - hvv);
+  }
+  t0 = wf * f0v;
+  t1 = wf * f1v;
+  t2 = wf * f2v;
+}
+
 template <typename real, int N, int R, int P, bool FACE>
-__device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int b, int p, Lds<real, N> &L) {
+__device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int b, int p, Lds<real, N> &L, bool iface) {
   constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
   // volume rows: all Nh columns (the diagonal of the skew operator is zero);
   // face rows: the Nq volume columns (the surface-surface block is zero)
@@ -418,7 +463,6 @@ __device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int 
   const int r0 = b * R;                       // first row within the row set
   const int m0 = FACE ? Nq + r0 : r0;         // first hybrid-node index
   const real *Stab = FACE ? L.FT : L.ST;
-  const real g = real(d.g);
   typedef real real4 __attribute__((ext_vector_type(4)));
   const real *rbase = L.rec + e * Nh * kNodeRec;
   // Row m accumulates, over its columns n, c = Qx {hu} + Qy {hv} (a0), u_n c and v_n c (b1,
@@ -463,35 +507,14 @@ __device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int 
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int m = m0 + r;
-    if (FACE && p == 0) {
-      // interface flux W_f [ nJ . f_S(u~, u~+) + 1/2 g h (H+ - Href) nJ ] - LF penalty
+    if (FACE && p == 0 && iface) {         // interface terms of face row m (else a later pass)
       const int f = r0 + r;
-      const real *rm = rbase + m * kNodeRec;
-      const real wf = L.wf[f], nrf = L.nr[f], nsf = L.ns[f];
-      const real nJx = rx[r] * nrf + sx[r] * nsf, nJy = ry[r] * nrf + sy[r] * nsf;
-      const real h = rm[10], uu = real(2) * u[r], vv = real(2) * v[r], dH = rm[9];
-      const real huu = real(2) * hu[r], hvv = real(2) * hv[r];
-      const real *nbp = L.nb + (e * Nfq + f) * 4;
-      const real hP = nbp[0], uP = nbp[1], vP = nbp[2], dHP = nbp[3];
-      const real huP = hP * uP, hvP = hP * vP;
-      const real hua = real(0.5) * (huu + huP), hva = real(0.5) * (hvv + hvP);
-      const real ua = real(0.5) * (uu + uP), va = real(0.5) * (vv + vP);
-      const real pr = gh[r] * dHP;
-      real f0v = nJx * hua + nJy * hva;
-      real f1v = nJx * (hua * ua + pr) + nJy * hva * ua;
-      real f2v = nJx * hua * va + nJy * (hva * va + pr);
-      if (d.flux == 1) {
-        const real sJ = sqrt(nJx * nJx + nJy * nJy);
-        const real lm = fabs(uu * nJx + vv * nJy) + sqrt(g * h) * sJ;
-        const real lp = fabs(uP * nJx + vP * nJy) + sqrt(g * hP) * sJ;
-        const real c = real(0.5) * fmax(lm, lp);
-        f0v -= c * (dHP - dH);
-        f1v -= c * (huP - huu);
-        f2v -= c * (hvP - hvv);
-      }
-      a0[r] += wf * f0v;
-      a1[r] += wf * f1v;
-      a2[r] += wf * f2v;
+      real t0, t1, t2;
+      interface_terms<real>(rbase + m * kNodeRec, L.nb + (e * Nfq + f) * 4, L.wf[f], L.nr[f], L.ns[f], real(d.g),
+                            d.flux, t0, t1, t2);
+      a0[r] = a0[r] + t0;
+      a1[r] = a1[r] + t1;
+      a2[r] = a2[r] + t2;
     }
     real *Rp = L.R + p * 3 * ne * Nh;     // partial sums of column part p
     Rp[0 * ne * Nh + e * Nh + m] = a0[r];
@@ -504,42 +527,98 @@ __device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int 
 // the P partial sums are added in the lift.  One flat task list: first every volume
 // task, then every face task, so whole waves take the same branch.
 template <typename real, int N, int R, int P>
-__device__ __forceinline__ void residual_tile(const InstDesc &d, int ne, Lds<real, N> &L) {
+__device__ __forceinline__ void residual_tile(const InstDesc &d, int ne, Lds<real, N> &L, bool iface) {
   constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N);
   constexpr int VB = Nq / R, FB = Nfq / R;
   static_assert(Nq % R == 0 && Nfq % R == 0, "R must divide Nq and Nfq");
   static_assert(6 * dim_Nh(N) + 3 * dim_Np(N) <= 8 * dim_Nh(N) || P == 1, "partials must fit the raw block");
-  const int tid = threadIdx.x, nth = blockDim.x;
+  const int tid = phase_tid(), nth = blockDim.x;
   const int nv = ne * VB * P, ntask = nv + ne * FB * P;
   for (int t = tid; t < ntask; t += nth) {
     if (t < nv) {
       const int p = t % P, rest = t / P, e = rest / VB;
-      row_block<real, N, R, P, false>(d, ne, e, rest - e * VB, p, L);
+      row_block<real, N, R, P, false>(d, ne, e, rest - e * VB, p, L, iface);
     } else {
       const int tf = t - nv, p = tf % P, rest = tf / P, e = rest / FB;
-      row_block<real, N, R, P, true>(d, ne, e, rest - e * FB, p, L);
+      row_block<real, N, R, P, true>(d, ne, e, rest - e * FB, p, L, iface);
     }
   }
 }
 
+// Descriptors, tiles and tile ranges are written by the host before a launch and only
+// read by kernels.  Reading them through the constant address space lets the compiler use
+// scalar loads (lgkmcnt); as vector loads they would share vmcnt with the asynchronous
+// LDS copies, and every descriptor field needed between two copies would wait for all
+// copies issued before it.
+template <typename T>
+__device__ __forceinline__ const T &read_const(const T *p, int i) {
+  return *(const T *)((const __attribute__((address_space(4))) T *)p + i);
+}
+
+// Multi-stage launches: before stage `target` of tile t, wait until every tile holding a
+// face neighbour of t has published `target` completed stages (their projection has pushed
+// t's neighbour values, and they have finished reading the slots t is about to fill).
+// Wave 0 polls, one neighbour per lane, with device-coherent loads and a bounded spin; the
+// barrier then releases the other waves.  The neighbour values themselves are read with
+// device-coherent copies (fetch_tile), so no cache-wide invalidation is needed.  Returns
+// false (for the whole workgroup) if a wait gave up.
+__device__ __forceinline__ bool wait_neighbours(const StageArgs &a, int t, int target) {
+  int ok = 1;
+  if (threadIdx.x < 64) {
+    const int b = read_const(a.nbr_off, t), e = read_const(a.nbr_off, t + 1);
+    for (int j = b + int(threadIdx.x); j < e; j += 64) {
+      const int u = read_const(a.nbr_idx, j);
+      int spins = 0;
+      while (__hip_atomic_load(a.progress + u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++spins > a.spin_limit) { ok = 0; break; }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+  }
+  return __syncthreads_and(ok) != 0;
+}
+
+// After a stage of tile t: every wave waits until its stores have completed (the pushed
+// face values are device-coherent stores, so completion means visible to every XCD), then
+// one thread publishes the tile's completed-stage count.  The tile's other outputs are read
+// back only by this workgroup.
+__device__ __forceinline__ void publish(const StageArgs &a, int t, int value) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(a.progress + t, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Phase 3: interface terms of the face rows (Section 2.8), added to the first column
+// part of the residual: W_f [ nJ . f_S(u~, u~+) + 1/2 g h (H+ - Href) nJ ] - LF penalty,
+// one task per (element, face node).  A separate pass so that a resident tile can run
+// the whole pair loop before it waits for its neighbours' values.
+template <typename real, int N>
+__device__ __forceinline__ void interface_tile(const InstDesc &d, int ne, Lds<real, N> &L) {
+  constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
+  for (int i = phase_tid(); i < ne * Nfq; i += blockDim.x) {
+    const int e = i / Nfq, f = i - e * Nfq, m = Nq + f;
+    real t0, t1, t2;
+    interface_terms<real>(L.rec + (e * Nh + m) * kNodeRec, L.nb + (e * Nfq + f) * 4, L.wf[f], L.nr[f], L.ns[f],
+                          real(d.g), d.flux, t0, t1, t2);
+    real *R0 = L.R + e * Nh + m;          // column part 0 of the three fields
+    R0[0] = R0[0] + t0;
+    R0[ne * Nh] = R0[ne * Nh] + t1;
+    R0[2 * ne * Nh] = R0[2 * ne * Nh] + t2;
+  }
+}
+
 template <typename real, int N, int R, int CM>
-__device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm, real *tile,
-                                           int res = 0) {
+__device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm, real *tile,
+                                           int res = 0, int t = 0, int target = 0) {
   constexpr int Np = dim_Np(N), Nh = dim_Nh(N), Nfq = dim_Nfq(N);
-  const int tid = threadIdx.x, nth = blockDim.x;
+  const int tid = phase_tid(), nth = blockDim.x;
   Lds<real, N> L(sm, tile, ne);
   const real g = real(d.g);
   const bool mid = res & kResMid;                // resident tile after its first stage
   const bool keep = (res & kResident) && !(res & kResLast);   // state stays in LDS only
-  if (mid) {
-    // everything but the neighbour values is still in LDS from the previous stage
-    async_copy_words<kCpolAgent>(reinterpret_cast<uint32_t *>(L.nb),
-                                 static_cast<const uint32_t *>(d.nbx[a.in_buf]) + size_t(k0) * Nfq * 4 * (sizeof(real) / 4),
-                                 ne * Nfq * 4 * int(sizeof(real) / 4));
-    __builtin_amdgcn_s_waitcnt(0);
-  } else {
-    fetch_tile<real, N>(a, d, k0, ne, L);
-  }
+  // a resident tile after its first stage has everything but the neighbour values in LDS;
+  // it fetches those after the pair loop, once its neighbours have pushed them
+  if (!mid) fetch_tile<real, N>(a, d, k0, ne, L);
   // head of the static block: loaded into registers now, while the node records and the
   // residual run, and written to LDS before the barrier that ends the residual
   constexpr int W = sizeof(real) / 4;
@@ -558,7 +637,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
     __syncthreads();
     project_tile<real, N, CM>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]),
                               static_cast<real *>(d.nbx[a.out_buf]), a.flag, a.progress != nullptr);
-    return;
+    return true;
   }
   __syncthreads();
   // phase 1: node records from the fetched u~ and metric factors (a resident tile's
@@ -572,7 +651,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
     rec[2] = real4{real(0.5) * g * h, dH, h, real(0)};
   }
   __syncthreads();
-  residual_tile<real, N, R, ColParts<N>::value>(d, ne, L);
+  residual_tile<real, N, R, ColParts<N>::value>(d, ne, L, !mid);
   if (!mid) {
     uint32_t *sl = reinterpret_cast<uint32_t *>(L.Minv);
 #pragma unroll
@@ -580,6 +659,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
       const int v = tid + j * kBlock;
       if (v < head) sl[v] = sreg[j];
     }
+  } else {
+    if (!wait_neighbours(a, t, target)) return false;
+    async_copy_words<kCpolAgent>(reinterpret_cast<uint32_t *>(L.nb),
+                                 static_cast<const uint32_t *>(d.nbx[a.in_buf]) + size_t(k0) * Nfq * 4 * W,
+                                 ne * Nfq * 4 * W);
+    __builtin_amdgcn_s_waitcnt(0);
+  }
+  if (mid) {
+    __syncthreads();
+    interface_tile<real, N>(d, ne, L);
   }
   __syncthreads();
   // lift: y = V_h^T r_h (r_h = sum of the P partials), one task per (field, element, mode)
@@ -643,52 +732,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs &a, const InstDesc &d
     project_tile<real, N, CM>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]),
                               static_cast<real *>(d.nbx[a.out_buf]), a.flag, a.progress != nullptr, res);
   }
+  return true;
 }
 
 
-
-// Descriptors, tiles and tile ranges are written by the host before a launch and only
-// read by kernels.  Reading them through the constant address space lets the compiler use
-// scalar loads (lgkmcnt); as vector loads they would share vmcnt with the asynchronous
-// LDS copies, and every descriptor field needed between two copies would wait for all
-// copies issued before it.
-template <typename T>
-__device__ __forceinline__ const T &read_const(const T *p, int i) {
-  return *(const T *)((const __attribute__((address_space(4))) T *)p + i);
-}
-
-// Multi-stage launches: before stage `target` of tile t, wait until every tile holding a
-// face neighbour of t has published `target` completed stages (their projection has pushed
-// t's neighbour values, and they have finished reading the slots t is about to fill).
-// Wave 0 polls, one neighbour per lane, with device-coherent loads and a bounded spin; the
-// barrier then releases the other waves.  The neighbour values themselves are read with
-// device-coherent copies (fetch_tile), so no cache-wide invalidation is needed.  Returns
-// false (for the whole workgroup) if a wait gave up.
-__device__ __forceinline__ bool wait_neighbours(const StageArgs &a, int t, int target) {
-  int ok = 1;
-  if (threadIdx.x < 64) {
-    const int b = read_const(a.nbr_off, t), e = read_const(a.nbr_off, t + 1);
-    for (int j = b + int(threadIdx.x); j < e; j += 64) {
-      const int u = read_const(a.nbr_idx, j);
-      int spins = 0;
-      while (__hip_atomic_load(a.progress + u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        if (++spins > a.spin_limit) { ok = 0; break; }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-  }
-  return __syncthreads_and(ok) != 0;
-}
-
-// After a stage of tile t: every wave waits until its stores have completed (the pushed
-// face values are device-coherent stores, so completion means visible to every XCD), then
-// one thread publishes the tile's completed-stage count.  The tile's other outputs are read
-// back only by this workgroup.
-__device__ __forceinline__ void publish(const StageArgs &a, int t, int value) {
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(a.progress + t, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // Persistent stage kernel: block b walks a contiguous range of tiles.  Blocks are dealt
 // to the XCDs round-robin, so block b's range is chosen as range number
@@ -725,13 +772,15 @@ stage_kernel(StageArgs a) {
       as.rk_b = a.rk_b5[s % 5];
     }
     for (int t = t0; t < t1; ++t) {
-      if (multi && s > 0 && !wait_neighbours(a, t, a.stage0 + s)) {
+      const int res = resident ? kResident | (s > 0 ? kResMid : 0) | (s == nst - 1 ? kResLast : 0) : 0;
+      // non-resident tiles wait before the stage (they re-read their neighbours' values in
+      // the fetch); resident ones inside it, after their pair loop
+      if (multi && s > 0 && !(res & kResMid) && !wait_neighbours(a, t, a.stage0 + s)) {
         if (threadIdx.x == 0) atomicOr(a.flag, 2);
         return;
       }
       const Tile tl = read_const(a.tiles, t);
       const InstDesc &d = read_const(a.desc, tl.inst);
-      const int res = resident ? kResident | (s > 0 ? kResMid : 0) | (s == nst - 1 ? kResLast : 0) : 0;
       if (d.N != loaded_N) {
         __syncthreads();
         const real *ref = static_cast<const real *>(d.ref);
@@ -739,13 +788,18 @@ stage_kernel(StageArgs a) {
         for (int i = threadIdx.x; i < words; i += blockDim.x) sm[i] = ref[i];
         loaded_N = d.N;
       }
+      bool ok = true;
       switch (d.N) {
-        case 1: stage_tile<real, 1, RowsPerThread<1>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res); break;
-        case 2: stage_tile<real, 2, RowsPerThread<2>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res); break;
-        case 3: stage_tile<real, 3, RowsPerThread<3>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res); break;
-        case 4: stage_tile<real, 4, RowsPerThread<4>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res); break;
-        case 5: stage_tile<real, 5, RowsPerThread<5>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res); break;
+        case 1: ok = stage_tile<real, 1, RowsPerThread<real, 1>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
+        case 2: ok = stage_tile<real, 2, RowsPerThread<real, 2>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
+        case 3: ok = stage_tile<real, 3, RowsPerThread<real, 3>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
+        case 4: ok = stage_tile<real, 4, RowsPerThread<real, 4>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
+        case 5: ok = stage_tile<real, 5, RowsPerThread<real, 5>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
         default: break;
+      }
+      if (!ok) {
+        if (threadIdx.x == 0) atomicOr(a.flag, 2);
+        return;
       }
       if (multi) publish(a, t, a.stage0 + s + 1);
       else __syncthreads();
