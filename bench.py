@@ -74,10 +74,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(w, prec, epb, step_mode):
+def measured_traffic(w, prec, epb, step_mode, stages_per_launch):
     """HBM bytes per RK stage (FETCH_SIZE and WRITE_SIZE, copy-calibrated) from a committed
-    counter summary taken for this kernel source, workload, tile size and launch mode, or
-    None when there is none."""
+    counter summary taken for this kernel source, workload, tile size, launch mode and number
+    of stages per launch (a multi-stage launch spreads its first fetch and last write over
+    its stages), or None when there is none."""
     for path in TRAFFIC_FILES:
         if not os.path.exists(path):
             continue
@@ -88,6 +89,8 @@ def measured_traffic(w, prec, epb, step_mode):
                     k, v = line.strip().split("=", 1)
                     kv[k] = v
         if kv.get("kernel_source_sha256") != kernel_source_hash() or int(kv.get("step_mode", -1)) != step_mode:
+            continue
+        if int(kv.get("stages_per_launch", -1)) != stages_per_launch:
             continue
         if not (w.N == 3 and w.K == 8192 and prec == "fp32" and epb == 8):
             continue
@@ -257,7 +260,9 @@ def main():
     peak_alu = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
     frac_alu = achieved_tf / peak_alu
     frac_hbm = achieved_gbs / PEAK_HBM_GBS
-    tr = measured_traffic(w, prec, epb_used.get(prec, 0), plans[prec]["step_mode"])
+    step_mode = plans[prec]["step_mode"]
+    stages_per_launch = 1 if step_mode == 0 else 5 * args.steps
+    tr = measured_traffic(w, prec, epb_used.get(prec, 0), step_mode, stages_per_launch)
     # which roof binds: with measured traffic, the HBM side is what the kernel really moves
     # (tiles resident in LDS move far less than the algorithmic bytes); else the larger of
     # the two algorithmic fractions
@@ -275,13 +280,16 @@ def main():
                                   "counters": "FETCH_SIZE x2.0 + WRITE_SIZE x1.0 (copy-calibrated)",
                                   "source": tr["source"]}
     roof["kernel"] = "stage_kernel (fused RK stage: flux differencing + interface + lift + update + projection)"
-    roof["per_launch"] = {"alg_flops": flops, "alg_bytes": byts, "duration_us": round(t_stage * 1e6, 3),
-                          "duration_source": "HIP events on the solver stream over the timed steps, per RK stage "
-                                             "(rocprofv3 kernel traces of the same command: "
-                                             "profiles/stage_kernel_curved_N3_K8192.md)",
-                          "other_bound": ({"hbm_GBs": round(achieved_gbs, 1), "frac": round(frac_hbm, 4)}
-                                          if roof["bound"] == "alu" else
-                                          {"alu_TFLOPs": round(achieved_tf, 3), "frac": round(frac_alu, 4)})}
+    # a multi-stage launch covers 5 * steps stages: its algorithmic work and its duration are
+    # both that many stages', so the per-stage figures give the same rates
+    roof["per_stage"] = {"alg_flops": flops, "alg_bytes": byts, "duration_us": round(t_stage * 1e6, 3),
+                         "stages_per_launch": stages_per_launch,
+                         "duration_source": "HIP events on the solver stream over the timed steps, per RK stage "
+                                            "(rocprofv3 kernel traces of the same command: "
+                                            "profiles/stage_kernel_curved_N3_K8192.md)",
+                         "other_bound": ({"hbm_GBs": round(achieved_gbs, 1), "frac": round(frac_hbm, 4)}
+                                         if roof["bound"] == "alu" else
+                                         {"alu_TFLOPs": round(achieved_tf, 3), "frac": round(frac_alu, 4)})}
     out = {
         "metric": "DOF-updates/s per RK stage at N=3; FP32/batched vs FP64 speedup at stated error",
         "value": value,

@@ -1,0 +1,57 @@
+"""Host-side checks of bench.py's bookkeeping (no GPU): the committed HBM counter summaries
+are picked only for the kernel source, workload, launch mode and stages per launch they
+were taken on."""
+import importlib.util
+import os
+import types
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_host", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _summaries(b):
+    out = []
+    for path in b.TRAFFIC_FILES:
+        if not os.path.exists(path):
+            continue
+        kv = {}
+        with open(path) as fh:
+            for line in fh:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.strip().split("=", 1)
+                    kv[k] = v
+        out.append((path, kv))
+    return out
+
+
+def test_traffic_summaries_well_formed():
+    b = _bench()
+    found = _summaries(b)
+    assert found, "no committed HBM counter summary"
+    for path, kv in found:
+        for key in ("kernel_source_sha256", "step_mode", "stages_per_launch", "fetch_bytes", "write_bytes"):
+            assert key in kv, (path, key)
+        assert int(kv["fetch_bytes"]) > 0 and int(kv["write_bytes"]) > 0
+        assert int(kv["step_mode"]) in (0, 1, 2)
+        assert (int(kv["stages_per_launch"]) == 1) == (int(kv["step_mode"]) == 0)
+
+
+def test_traffic_lookup_matches_only_its_configuration():
+    b = _bench()
+    w = types.SimpleNamespace(N=3, K=8192)
+    for path, kv in _summaries(b):
+        if kv["kernel_source_sha256"] != b.kernel_source_hash():
+            continue  # taken on an older kernel source: never reported
+        mode, spl = int(kv["step_mode"]), int(kv["stages_per_launch"])
+        tr = b.measured_traffic(w, "fp32", 8, mode, spl)
+        assert tr is not None and tr["fetch"] == int(kv["fetch_bytes"])
+        assert b.measured_traffic(w, "fp32", 8, mode, spl + 5) is None
+        assert b.measured_traffic(w, "fp64", 8, mode, spl) is None
+        assert b.measured_traffic(w, "fp32", 4, mode, spl) is None
+        assert b.measured_traffic(types.SimpleNamespace(N=4, K=8192), "fp32", 8, mode, spl) is None
