@@ -32,7 +32,10 @@ Readings where the paper is silent, garbled or ambiguous (all listed in DESIGN.m
 * Lax-Friedrichs penalty (Section 2.8): -1/2 lambda sJ W_f (u~+ - u~) on the
   entropy-projected conservative variables, lambda = max over both sides of
   |u.n| + sqrt(g h);
-* LSRK coefficients: the published Carpenter-Kennedy (1994) 2N-storage values.
+* LSRK coefficients: the published Carpenter-Kennedy (1994) 2N-storage values;
+* optional weight-adjusted mass inverse (the implementation remark after eq. (dgform),
+  Section 2.8): M^{-1} M_{1/J} M^{-1} in both the entropy projection and the lift, with
+  the projected entropy variables those of S - g Href h (Href a fixed reference level).
 """
 from __future__ import annotations
 
@@ -245,10 +248,24 @@ def equispaced_rs(N: int):
 
 
 class Discretization:
-    """Per-mesh data for one instance: geometry, connectivity and curved mass matrices."""
+    """Per-mesh data for one instance: geometry, connectivity and curved mass matrices.
+
+    ``mass`` selects how (M_h^k)^{-1} is applied wherever the scheme needs it (the
+    J-weighted entropy projection of Section 2.6 and the lift of Section 2.8):
+    "exact" solves with the curved mass matrix M_h^k = V_q^T W diag(J) V_q (Section 2.7);
+    "wadg" uses the weight-adjusted inverse that the paper names as the way to avoid
+    storing the per-element inverses (the implementation remark after eq. (dgform) in
+    Section 2.8, citing Chan & Wilcox): (M_h^k)^{-1} ~ M^{-1} M_{1/J} M^{-1}, with the reference
+    mass matrix M and M_{1/J} = V_q^T W diag(1/J) V_q.  It is exact where J is constant
+    on the element, and used in both places so that the projected entropy variables and
+    the time derivative see the same (approximate) mass matrix.
+    """
 
     def __init__(self, N: int, xg: np.ndarray, yg: np.ndarray, b_nodes: Optional[np.ndarray], g: float,
-                 Lx: float, Ly: float):
+                 Lx: float, Ly: float, mass: str = "exact"):
+        if mass not in ("exact", "wadg"):
+            raise ValueError("mass must be 'exact' or 'wadg'")
+        self.mass = mass
         ref = ReferenceElement(N)
         self.ref, self.N, self.g = ref, N, float(g)
         self.K = xg.shape[0]
@@ -281,6 +298,8 @@ class Discretization:
         wJ = ref.wq[None, :] * self.Jq
         self.Mh = np.einsum("qi,kq,qj->kij", ref.Vq, wJ, ref.Vq)
         self.Mh_chol = np.linalg.cholesky(self.Mh)
+        # weight-adjusted inverse: quadrature weights over J at the volume nodes
+        self.w_over_J = ref.wq[None, :] / self.Jq
         self.mapP = self._connect()
         # bathymetry: C0 nodal samples -> modes -> hybridized nodes
         if b_nodes is None:
@@ -335,13 +354,32 @@ class Discretization:
         return u_nodes @ self.Vgeo_inv.T
 
     def project(self, f_q: np.ndarray) -> np.ndarray:
-        """J-weighted quadrature L2 projection (M_h^k)^{-1} V_q^T W diag(J^k) f_q, per element."""
+        """J-weighted quadrature L2 projection (M_h^k)^{-1} V_q^T W diag(J^k) f_q, per element
+        (the weight-adjusted inverse with mass="wadg")."""
         ref = self.ref
         rhs = (f_q * (ref.wq[None, :] * self.Jq)) @ ref.Vq
         return self.mh_solve(rhs)
 
+    def ref_solve(self, r: np.ndarray) -> np.ndarray:
+        """Solve M x = r with the reference mass matrix, along the last axis of r."""
+        Np = self.ref.Np
+        flat = r.reshape(-1, Np)
+        return np.linalg.solve(self.ref.M, flat.T).T.reshape(r.shape)
+
+    def wadg_apply(self, r: np.ndarray, ks: np.ndarray) -> np.ndarray:
+        """x = M^{-1} M_{1/J} M^{-1} r for the elements ks (r has shape [..., len(ks), Np]):
+        the weight-adjusted approximation of (M_h^k)^{-1} r, applied as written, one
+        factor after the other."""
+        ref = self.ref
+        y = self.ref_solve(r)
+        t = (y @ ref.Vq.T) * self.w_over_J[ks]            # W diag(1/J) V_q y at the volume nodes
+        return self.ref_solve(t @ ref.Vq)
+
     def mh_solve_subset(self, r: np.ndarray, ks: np.ndarray) -> np.ndarray:
-        """Solve M_h^k x = r for the listed elements ks (r has shape [3, len(ks), Np])."""
+        """Solve M_h^k x = r for the listed elements ks (r has shape [3, len(ks), Np]);
+        with mass="wadg", apply the weight-adjusted inverse instead."""
+        if self.mass == "wadg":
+            return self.wadg_apply(r, ks)
         L = self.Mh_chol[ks]
         out = np.empty_like(r)
         for c in range(r.shape[0]):
@@ -350,7 +388,10 @@ class Discretization:
         return out
 
     def mh_solve(self, r: np.ndarray) -> np.ndarray:
-        """Solve M_h^k x = r for every element (r has shape [..., K, Np])."""
+        """Solve M_h^k x = r for every element (r has shape [..., K, Np]); with
+        mass="wadg", apply the weight-adjusted inverse instead."""
+        if self.mass == "wadg":
+            return self.wadg_apply(r, np.arange(self.K))
         L = self.Mh_chol
         shp = r.shape
         rr = r.reshape(-1, self.K, self.ref.Np)
@@ -420,12 +461,20 @@ def ec_flux(uL, uR, g):
 class Oracle:
     """Dense FP64 evaluation of eq. (dgform) with bathymetry source and optional LF penalty."""
 
-    def __init__(self, disc: Discretization, flux: str = "lf", chunk: int = 2048):
+    def __init__(self, disc: Discretization, flux: str = "lf", chunk: int = 2048, Href: float = 0.0):
+        """``Href``: the entropy whose variables are projected (Section 2.6) is taken as
+        S - g Href h, with entropy variables v - (g Href, 0, 0).  It differs from S by a
+        multiple of the conserved depth, so it is an entropy of the same system, and with
+        the exact mass inverse the result does not depend on Href (the J-weighted projection
+        reproduces constants).  The weight-adjusted inverse does not reproduce constants on
+        curved elements, so there the result depends on Href at the level of the
+        weight-adjustment error; a lake at rest at level Href then stays exactly at rest."""
         if flux not in ("ec", "lf"):
             raise ValueError("flux must be 'ec' or 'lf'")
         self.d = disc
         self.flux = flux
         self.chunk = chunk
+        self.Href = float(Href)
 
     # Section 2.6: entropy projection
     def entropy_projection(self, uh: np.ndarray):
@@ -436,8 +485,11 @@ class Oracle:
         d, ref, g = self.d, self.d.ref, self.d.g
         uq = uh @ ref.Vq.T                                     # [3,K,Nq]
         vq = np.stack(entropy_variables(uq[0], uq[1], uq[2], d.b_q, g))
+        vq[0] -= g * self.Href                                 # variables of S - g Href h
         vh = d.project(vq)
         vt = vh @ ref.Vh.T
+        vt[0] += g * self.Href
+        vh[:, :, 0] += g * self.Href * math.sqrt(2.0)          # the constant 1 is sqrt(2) phi_0
         ut = np.stack(conservative_from_entropy(vt[0], vt[1], vt[2], d.b_hyb, g))
         return ut, vh
 
@@ -545,6 +597,14 @@ def run(oracle: Oracle, uh: np.ndarray, dt: float, nsteps: int):
 # ----------------------------------------------------------------------------------
 # Diagnostics (Sections 2.4 and 2.7): conserved totals, entropy and its rate
 # ----------------------------------------------------------------------------------
+
+
+def mean_free_surface(disc: Discretization, uh: np.ndarray) -> float:
+    """J-weighted mean of h + b over the volume quadrature nodes (the reference level of a
+    state: sum w J (h + b) / sum w J)."""
+    wJ = disc.ref.wq[None, :] * disc.Jq
+    hq = uh[0] @ disc.ref.Vq.T
+    return float(np.sum(wJ * (hq + disc.b_q)) / np.sum(wJ))
 
 
 def diagnostics(oracle: Oracle, uh: np.ndarray) -> Dict[str, np.ndarray]:
