@@ -42,19 +42,21 @@ def dims(N):
     return Np, Nq, Nfq, Nq + Nfq
 
 
-def alg_flops_per_elem(N):
+def alg_flops_per_elem(N, wadg=False):
     """35 FLOP per unordered nonzero node pair (flux differencing) + projection and lift
-    contractions 6(2 Nq Np + Np^2 + Nh Np) + 6(Np Nh + Np^2)."""
+    contractions 6(2 Nq Np + Np^2 + Nh Np) + 6(Np Nh + Np^2); with the weight-adjusted mass
+    inverse each Np^2 (the stored inverse) becomes 2 Nq Np (two contractions with V_q)."""
     Np, Nq, Nfq, Nh = dims(N)
-    return 35 * pairs(N) + 6 * (2 * Nq * Np + Np * Np + Nh * Np) + 6 * (Np * Nh + Np * Np)
+    m = 2 * Nq * Np if wadg else Np * Np
+    return 35 * pairs(N) + 6 * (2 * Nq * Np + m + Nh * Np) + 6 * (Np * Nh + m)
 
 
-def alg_bytes_per_elem(N, word):
+def alg_bytes_per_elem(N, word, wadg=False):
     """Minimum HBM bytes per element per stage: state 12 Np words (read u_h; read and write
     du; write u_h), face exchange 6 Nfq, geometry 2 Np (node coordinates), bathymetry Np,
-    and the curved inverse mass matrix Np^2."""
+    and the curved inverse mass matrix Np^2 (with the weight-adjusted inverse: w/J, Nq)."""
     Np, Nq, Nfq, Nh = dims(N)
-    return word * (12 * Np + 6 * Nfq + 2 * Np + Np + Np * Np)
+    return word * (12 * Np + 6 * Nfq + 2 * Np + Np + (Nq if wadg else Np * Np))
 
 
 TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
@@ -112,14 +114,14 @@ def time_steps(s, dt, steps, torch):
     return ev0.elapsed_time(ev1)
 
 
-def cpu_baseline(w, stages_budget=75):
+def cpu_baseline(w, stages_budget=75, mass="stored"):
     """The FP64 oracle as it stands, timed on this host: `stages_budget` RK stages of the
     same workload (one RHS + axpy each), BLAS pinned to one thread."""
     from threadpoolctl import threadpool_limits
     from oracle import esdg_oracle as O
-    d = O.Discretization(w.N, w.xg, w.yg, w.b_nodes, w.g, w.Lx, w.Ly)
-    o = O.Oracle(d, w.flux)
+    d = O.Discretization(w.N, w.xg, w.yg, w.b_nodes, w.g, w.Lx, w.Ly, mass="wadg" if mass == "wadg" else "exact")
     uh = d.interpolate(w.u_nodes)
+    o = O.Oracle(d, w.flux, Href=O.mean_free_surface(d, uh))
     du = np.zeros_like(uh)
     with threadpool_limits(1):
         t0 = time.perf_counter()
@@ -150,7 +152,7 @@ def ensemble(args, torch):
     for prec in ([args.precision] + ([] if args.no_fp64 else ["fp64"])):
         t0 = time.perf_counter()
         s = EsdgSwe(ws, precision=prec, flux="lf", g=1.0, use_graph=not args.no_graph,
-                    matrix_cores=args.matrix_cores, fused=FUSED_ARG[args.launch])
+                    matrix_cores=args.matrix_cores, fused=FUSED_ARG[args.launch], mass=args.mass)
         for i, w in enumerate(ws):
             s.set_state(i, w.u_nodes)
         print(f"# {prec}: planned and set in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -194,6 +196,9 @@ def main():
                     help="per-stage: one launch per RK stage (graph replays); fused: all stages of a step "
                          "call in one cooperative launch with neighbour-tile waits; auto (default): fused "
                          "when every workgroup holds one tile, which then stays in LDS")
+    ap.add_argument("--mass", choices=["stored", "wadg"], default="stored",
+                    help="inverse curved mass matrices: stored per element (default), or the "
+                         "weight-adjusted inverse (w/J per volume node)")
     ap.add_argument("--matrix-cores", action="store_true",
                     help="projection/lift contractions on the matrix cores in the bulk precision")
     ap.add_argument("--ensemble", type=int, default=0,
@@ -233,7 +238,7 @@ def main():
     precs = [args.precision] + ([] if args.no_fp64 or args.precision == "fp64" else ["fp64"])
     for prec in precs:
         s = EsdgSwe([w], precision=prec, flux=w.flux, g=w.g, elems_per_block=args.epb, use_graph=not args.no_graph,
-                    matrix_cores=args.matrix_cores, fused=FUSED_ARG[args.launch])
+                    matrix_cores=args.matrix_cores, fused=FUSED_ARG[args.launch], mass=args.mass)
         plans[prec] = s.launch_info()
         e = s.elems_per_block
         epb_used[prec] = int(e.get(w.N, 0)) if isinstance(e, dict) else int(e or 0)
@@ -253,8 +258,9 @@ def main():
     t_stage = ms * 1e-3 / (5 * args.steps)
     value = dof / t_stage
     word = 8 if prec == "fp64" else 4
-    flops = alg_flops_per_elem(w.N) * w.K
-    byts = alg_bytes_per_elem(w.N, word) * w.K
+    wadg = args.mass == "wadg"
+    flops = alg_flops_per_elem(w.N, wadg) * w.K
+    byts = alg_bytes_per_elem(w.N, word, wadg) * w.K
     achieved_tf = flops / t_stage / 1e12
     achieved_gbs = byts / t_stage / 1e9
     peak_alu = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
@@ -262,7 +268,7 @@ def main():
     frac_hbm = achieved_gbs / PEAK_HBM_GBS
     step_mode = plans[prec]["step_mode"]
     stages_per_launch = 1 if step_mode == 0 else 5 * args.steps
-    tr = measured_traffic(w, prec, epb_used.get(prec, 0), step_mode, stages_per_launch)
+    tr = None if wadg else measured_traffic(w, prec, epb_used.get(prec, 0), step_mode, stages_per_launch)
     # which roof binds: with measured traffic, the HBM side is what the kernel really moves
     # (tiles resident in LDS move far less than the algorithmic bytes); else the larger of
     # the two algorithmic fractions
@@ -308,6 +314,7 @@ def main():
                    "K": w.K, "N": w.N, "DOF": dof, "precision": prec, "hip_graph": not args.no_graph,
                    "elements_per_workgroup": epb_used.get(prec, 0),
                    "matrix_cores": bool(args.matrix_cores or prec == "bf16x3"),
+                   "mass_inverse": {"stored": "stored per element", "wadg": "weight-adjusted"}[args.mass],
                    "launch": STEP_MODES[plans[prec]["step_mode"]],
                    "workgroups": plans[prec]["resident_workgroups"], "tiles": plans[prec]["tiles"]},
         "roofline": roof,
@@ -327,7 +334,7 @@ def main():
             "hv": float(np.linalg.norm(a[2] - b[2]) / max(np.linalg.norm(b[2]), 1e-300)),
         }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, mass=args.mass)
     print(json.dumps(out), flush=True)
 
 

@@ -83,6 +83,25 @@ enum {
   ESDG_FLUX_LF = 1      /* plus local Lax-Friedrichs penalty on entropy-projected variables */
 };
 
+/* how the inverse curved mass matrices (M_h^k)^{-1} = (V_q^T W diag(J) V_q)^{-1} of Section
+ * 2.7 are applied, in the entropy projection (Section 2.6) and in the lift (Section 2.8) */
+enum {
+  ESDG_MASS_STORED = 0,           /* precomputed per element and stored, Np x Np reals each   */
+  ESDG_MASS_WEIGHT_ADJUSTED = 1   /* weight-adjusted inverse M^{-1} M_{1/J} M^{-1}, M_{1/J} =
+                                     V_q^T W diag(1/J) V_q (the alternative the paper names
+                                     after eq. (dgform), Section 2.8): only w/J at the Nq volume
+                                     nodes is stored per element.  Exact where J is constant on
+                                     the element, otherwise an approximation that agrees with
+                                     the stored inverse to first order in the variation of J.
+                                     Used in both places, the scheme keeps its entropy
+                                     conservation (EC flux) and dissipation (LF).  The
+                                     projected entropy variables are those of S - g Href h
+                                     (Href: esdg_swe_reference_level), so a lake at rest at
+                                     that level stays exactly at rest.  The mass reported by
+                                     esdg_swe_diagnostics (the J-weighted integral of h) is then
+                                     conserved only to the accuracy of the weight adjustment. */
+};
+
 /* One independent shallow-water instance on a periodic box. */
 typedef struct {
   int32_t N;            /* polynomial (and geometry) degree, 1..5                          */
@@ -115,12 +134,13 @@ typedef struct {
                                one tile, else 0.  With 1 (or 2 resolving to 1) bind fails with
                                ESDG_EDEVICE where cooperative launch is missing.  Results are
                                bitwise the same in every mode.                                */
+  int32_t mass_inverse;     /* ESDG_MASS_STORED | ESDG_MASS_WEIGHT_ADJUSTED                   */
 } esdg_swe_options;
 
 /* Plan a solver for n_inst independent instances (n_inst = 1 for a single run).  Builds,
  * on the host in double precision, the reference operators of each degree, the
  * isoparametric geometry, the periodic face connectivity and the inverse curved mass
- * matrices (Sections 2.1-2.7).  Validates: 1 <= N <= 5, J > 0 at every quadrature node,
+ * matrices, or with ESDG_MASS_WEIGHT_ADJUSTED the weights w/J (Sections 2.1-2.7).  Validates: 1 <= N <= 5, J > 0 at every quadrature node,
  * every face node matched.  On success *out is a new handle and *workspace_bytes the
  * device workspace size esdg_swe_bind needs.  No device call is made. */
 esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const esdg_swe_options *opt,

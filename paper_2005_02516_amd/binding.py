@@ -36,14 +36,15 @@ class esdg_swe_instance(C.Structure):
 class esdg_swe_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("flux", C.c_int32), ("g", C.c_double),
                 ("use_graph", C.c_int32), ("elems_per_block", C.c_int32 * 6), ("matrix_cores", C.c_int32),
-                ("fused_steps", C.c_int32)]
+                ("fused_steps", C.c_int32), ("mass_inverse", C.c_int32)]
 
 
 FUSED = {False: 0, True: 1, "auto": 2}
+MASS = {"stored": 0, "wadg": 1}      # inverse curved mass matrices: stored, or weight-adjusted
 
 
 def make_options(precision: str, flux: str, g: float, use_graph: bool = True, epb=None,
-                 matrix_cores: bool = False, fused="auto") -> esdg_swe_options:
+                 matrix_cores: bool = False, fused="auto", mass: str = "stored") -> esdg_swe_options:
     """epb: None, an int (all degrees) or a mapping N -> elements per workgroup."""
     arr = (C.c_int32 * 6)()
     if isinstance(epb, int):
@@ -53,7 +54,7 @@ def make_options(precision: str, flux: str, g: float, use_graph: bool = True, ep
         for N, E in epb.items():
             arr[int(N)] = int(E)
     return esdg_swe_options(PRECISIONS[precision], FLUXES[flux], float(g), int(use_graph), arr,
-                            2 if matrix_cores else 1, FUSED[fused])
+                            2 if matrix_cores else 1, FUSED[fused], MASS[mass])
 
 
 class EsdgError(RuntimeError):
@@ -113,7 +114,8 @@ class EsdgSwe:
 
     def __init__(self, instances: Sequence, precision: str = "fp64", flux: str = "lf", g: float = 1.0,
                  elems_per_block=None, use_graph: bool = True, device: str = "cuda:0", stream=None,
-                 tuned: bool = True, matrix_cores: Optional[bool] = None, fused: Optional[bool] = None):
+                 tuned: bool = True, matrix_cores: Optional[bool] = None, fused: Optional[bool] = None,
+                 mass: str = "stored"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("EsdgSwe needs a GPU: the library has no CPU path")
@@ -136,7 +138,8 @@ class EsdgSwe:
         if fused is None:       # one launch per step call when tiles can stay resident
             fused = {"0": False, "1": True}.get(os.environ.get("ESDG_SWE_FUSED", ""), "auto")
         self.elems_per_block = elems_per_block
-        opt = make_options(precision, flux, g, use_graph, elems_per_block, matrix_cores, fused)
+        opt = make_options(precision, flux, g, use_graph, elems_per_block, matrix_cores, fused, mass)
+        self.mass = mass
         h = C.c_void_p()
         nbytes = C.c_size_t()
         st = self.lib.esdg_swe_init(len(instances), arr, C.byref(opt), C.byref(h), C.byref(nbytes))

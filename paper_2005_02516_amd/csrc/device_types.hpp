@@ -35,20 +35,27 @@ __host__ __device__ constexpr int ref_words(int N) {
   return dim_Nh(N) * dim_Np(N) + 2 * dim_Nh(N) * dim_Nq(N) + 2 * dim_Nq(N) * dim_Nfq(N) + 3 * dim_Nfq(N);
 }
 
-// Words (of the bulk precision) of LDS one tile of E elements of degree N needs (the
-// reference block is held separately, once per workgroup): node records [E][Nh][kNodeRec] | fetched u~ and metrics [8][E][Nh] |
-// neighbour values [E][Nfq][4] | state, RK register [3][E][Np] each | Minv [E][Np][Np] |
-// w J [E][Nq] | b at volume nodes [E][Nq] | b at hybrid nodes [E][Nh] | push targets
-// [E][Nfq] (int32, one word of the bulk precision each).
-__host__ __device__ constexpr int tile_words(int N, int E) {
-  return E * (dim_Nh(N) * kNodeRec + 8 * dim_Nh(N) + 4 * dim_Nfq(N) + 6 * dim_Np(N) +
-                             dim_Np(N) * dim_Np(N) + 2 * dim_Nq(N) + dim_Nh(N) + dim_Nfq(N));
+// Reals per element of the mass-matrix data: the stored inverse (M_h^k)^{-1} [Np][Np], or,
+// with the weight-adjusted inverse, the quadrature weights over J at the volume nodes [Nq].
+__host__ __device__ constexpr int mass_words(int N, bool wadg) {
+  return wadg ? dim_Nq(N) : dim_Np(N) * dim_Np(N);
 }
 
-// Reals per element of the static per-tile block (see InstDesc::stat): Minv, w J, b at the
-// volume and at the hybrid nodes, and the face push targets (int32, one real-sized slot each).
-__host__ __device__ constexpr int stat_words(int N) {
-  return dim_Np(N) * dim_Np(N) + 2 * dim_Nq(N) + dim_Nh(N) + dim_Nfq(N);
+// Words (of the bulk precision) of LDS one tile of E elements of degree N needs (the
+// reference block is held separately, once per workgroup): node records [E][Nh][kNodeRec] | fetched u~ and metrics [8][E][Nh] |
+// neighbour values [E][Nfq][4] | state, RK register [3][E][Np] each | mass data
+// [E][mass_words] | w J [E][Nq] | b at volume nodes [E][Nq] | b at hybrid nodes [E][Nh] |
+// push targets [E][Nfq] (int32, one word of the bulk precision each).
+__host__ __device__ constexpr int tile_words(int N, int E, bool wadg = false) {
+  return E * (dim_Nh(N) * kNodeRec + 8 * dim_Nh(N) + 4 * dim_Nfq(N) + 6 * dim_Np(N) +
+                             mass_words(N, wadg) + 2 * dim_Nq(N) + dim_Nh(N) + dim_Nfq(N));
+}
+
+// Reals per element of the static per-tile block (see InstDesc::stat): the mass data, w J,
+// b at the volume and at the hybrid nodes, and the face push targets (int32, one real-sized
+// slot each).
+__host__ __device__ constexpr int stat_words(int N, bool wadg = false) {
+  return mass_words(N, wadg) + 2 * dim_Nq(N) + dim_Nh(N) + dim_Nfq(N);
 }
 
 // 32-bit words per thread of the static block that a stage stages through registers
@@ -72,7 +79,8 @@ struct InstDesc {
   const void *wJq;     // [K][Nq] w_q J (diagnostics)
   const void *bq;      // [K][Nq] bathymetry at volume nodes (diagnostics)
   const void *stat;    // static data in tile order: the tile of elements k0..k0+ne-1 holds, from
-                       // real k0 * stat_words(N): Minv [ne][Np][Np] | w J [ne][Nq] | b [ne][Nq] |
+                       // real k0 * stat_words(N, wadg): the mass data [ne][mass_words] (Minv
+                       // [Np][Np], or w/J at the volume nodes [Nq]) | w J [ne][Nq] | b [ne][Nq] |
                        // b [ne][Nh] | push targets [ne][Nfq] (int32 k'*Nfq + f' of the nbx slot
                        // that face node f fills, packed in the first ne*Nfq 32-bit words)
   const void *ref;     // reference-operator block for this N
@@ -98,6 +106,8 @@ struct StageArgs {
   int32_t ref_words_max;  // LDS words reserved for the reference block (largest degree)
   int32_t contraction;    // constant-matrix contractions: 0 VALU, 1 matrix cores in the bulk
                           // precision, 2 matrix cores with split-bf16 products
+  int32_t wadg;           // 0: stored inverse mass matrices; 1: weight-adjusted inverse
+  int32_t pad_w;
   const int32_t *ranges;  // optional [grid+1]: tile range of each block's chunk (cost-balanced);
                           // null means equal numbers of tiles per chunk
   int32_t in_buf, out_buf;

@@ -303,12 +303,14 @@ void nodes_to_modes(const RefElem &R, int K, const double *u, double *uh) {
 }
 
 std::string build_instance(const RefElem &R, int K, const double *xg, const double *yg, const double *b, double Lx,
-                           double Ly, InstanceHost &out) {
+                           double Ly, InstanceHost &out, bool want_minv) {
   const int Np = R.Np, Nq = R.Nq, Nh = R.Nh, Nfp = R.Nfp, Nfq = R.Nfq;
   out.N = R.N; out.K = K; out.Lx = Lx; out.Ly = Ly;
   out.geo.assign(size_t(4) * K * Nh, 0.0);
   out.wJq.assign(size_t(K) * Nq, 0.0);
-  out.Minv.assign(size_t(K) * Np * Np, 0.0);
+  if (want_minv) out.Minv.assign(size_t(K) * Np * Np, 0.0);
+  else out.Minv.clear();
+  out.wOverJ.assign(size_t(K) * Nq, 0.0);
   out.bq.assign(size_t(K) * Nq, 0.0);
   out.bh.assign(size_t(K) * Nh, 0.0);
   out.bmodal.assign(size_t(K) * Np, 0.0);
@@ -356,7 +358,9 @@ std::string build_instance(const RefElem &R, int K, const double *xg, const doub
       }
       Jmin = std::min(Jmin, J[q]); Jmax = std::max(Jmax, J[q]);
       out.wJq[size_t(k) * Nq + q] = R.wq[q] * J[q];
+      out.wOverJ[size_t(k) * Nq + q] = R.wq[q] / J[q];
     }
+    if (!want_minv) continue;
     for (int i = 0; i < Np; ++i)
       for (int j = 0; j < Np; ++j) {
         double v = 0.0;

@@ -43,7 +43,8 @@ struct InstanceHost {
   double Lx = 0, Ly = 0;
   std::vector<double> geo;    // [4][K][Nh]: rxJ, sxJ, ryJ, syJ (J-scaled metric cofactors)
   std::vector<double> wJq;    // [K][Nq]: w_q * J at volume nodes
-  std::vector<double> Minv;   // [K][Np][Np]: (V_q^T W diag(J) V_q)^{-1}
+  std::vector<double> Minv;   // [K][Np][Np]: (V_q^T W diag(J) V_q)^{-1} (empty when not needed)
+  std::vector<double> wOverJ; // [K][Nq]: w_q / J at volume nodes (weight-adjusted inverse)
   std::vector<double> bq;     // [K][Nq]: bathymetry at volume nodes
   std::vector<double> bh;     // [K][Nh]: bathymetry at hybrid nodes
   std::vector<double> bmodal; // [K][Np]: modal coefficients of the bathymetry
@@ -51,9 +52,10 @@ struct InstanceHost {
   double Jmin = 0, Jmax = 0;
 };
 
-// Returns "" on success or an error message.  xg, yg, b are [K][Np] (b may be null).
+// Returns "" on success or an error message.  xg, yg, b are [K][Np] (b may be null).  With
+// want_minv false the inverse curved mass matrices are not formed (weight-adjusted inverse).
 std::string build_instance(const RefElem &ref, int K, const double *xg, const double *yg, const double *b,
-                           double Lx, double Ly, InstanceHost &out);
+                           double Lx, double Ly, InstanceHost &out, bool want_minv = true);
 
 // Modal coefficients of the interpolant through equispaced-node samples: out[k][i].
 void nodes_to_modes(const RefElem &ref, int K, const double *u_nodes, double *uh);

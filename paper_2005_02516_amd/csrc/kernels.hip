@@ -149,8 +149,9 @@ struct Lds {
   real *rec, *raw, *nb, *U, *DU, *Minv, *wJ, *bq, *bh;
   real *R, *T, *Q, *VH;
   int32_t *pp;
-  // sm: the ref block (already loaded); tile: the tile region (after the largest ref block)
-  __device__ Lds(real *sm, real *tile, int E) {
+  // sm: the ref block (already loaded); tile: the tile region (after the largest ref block);
+  // mw: reals of mass data per element (mass_words)
+  __device__ Lds(real *sm, real *tile, int E, int mw) {
     ref = sm;
     Vh = ref;
     ST = Vh + Nh * Np;
@@ -164,7 +165,7 @@ struct Lds {
     U = nb + 4 * E * Nfq;
     DU = U + 3 * E * Np;
     Minv = DU + 3 * E * Np;
-    wJ = Minv + E * Np * Np;
+    wJ = Minv + E * mw;          // Minv: [E][Np][Np], or w/J [E][Nq] (weight-adjusted)
     bq = wJ + E * Nq;
     bh = bq + E * Nq;
     pp = reinterpret_cast<int32_t *>(bh + E * Nh);
@@ -194,15 +195,55 @@ constexpr int kResident = 1;       // the tile's records, metric factors, static
 constexpr int kResMid = 2;         // not the first stage: only the neighbour values are fetched
 constexpr int kResLast = 4;        // last stage: the state, RK register and u~ go to HBM
 
+// Weight-adjusted inverse of the curved mass matrix (the implementation remark after eq.
+// (dgform) in Section 2.8): (M_h^k)^{-1} y ~ M^{-1} M_{1/J} M^{-1} y with M_{1/J} =
+// V_q^T W diag(1/J) V_q; the reference mass matrix M is the identity for the orthonormal
+// basis with the degree-2N volume rule, so this is V_q^T diag(w/J) V_q y, two contractions
+// with V_q (the first Nq rows of V_h) and the per-element weights w/J (held where the
+// stored inverse would be).  First factor, one task per (field, element, volume node):
+// S[c][e][q] = (w/J)[e][q] sum_j V_q[q][j] Y[c][e][j].
+template <typename real, int N>
+__device__ __forceinline__ void wadg_first(int ne, const Lds<real, N> &L, const real *Y, real *S) {
+  constexpr int Np = dim_Np(N), Nq = dim_Nq(N);
+  for (int i = phase_tid(); i < 3 * ne * Nq; i += blockDim.x) {
+    const int c = (i >= ne * Nq) + (i >= 2 * ne * Nq), r = i - c * ne * Nq, e = r / Nq, q = r - e * Nq;
+    const real *Yc = Y + c * ne * Np + e * Np;
+    const real *Vq = L.Vh + q * Np;
+    real a = 0, b = 0;
+#pragma unroll 4
+    for (int j = 0; j + 1 < Np; j += 2) {
+      a += Vq[j] * Yc[j];
+      b += Vq[j + 1] * Yc[j + 1];
+    }
+    if (Np & 1) a += Vq[Np - 1] * Yc[Np - 1];
+    S[i] = L.Minv[e * Nq + q] * (a + b);
+  }
+}
+
+// Second factor for one output mode: sum_q V_q[q][row] Sc[q].
+template <typename real, int N>
+__device__ __forceinline__ real wadg_second(const Lds<real, N> &L, const real *Sc, int row) {
+  constexpr int Np = dim_Np(N), Nq = dim_Nq(N);
+  real a = 0, b = 0;
+#pragma unroll 4
+  for (int q = 0; q + 1 < Nq; q += 2) {
+    a += L.Vh[q * Np + row] * Sc[q];
+    b += L.Vh[(q + 1) * Np + row] * Sc[q + 1];
+  }
+  if (Nq & 1) a += L.Vh[(Nq - 1) * Np + row] * Sc[Nq - 1];
+  return a + b;
+}
+
 // Entropy projection of the tile states in L.U ([3][ne][Np]: eta, hu, hv) to the
 // hybridized nodes (Section 2.6), written to out (tile-blocked [4][ne][Nh]: h~, u~, v~,
 // H~ - Href) or, in a resident stage that is not the last, straight into the node records
 // of the next stage (the same values the records phase would form from out):
 //   q = V_q u_h; h = eta_q + Href - b_q; v' = (g eta_q - |u|^2/2, u, v) = v(u_q) - (g Href, 0, 0)
-//   (FP64); v'_h = Minv_k V_q^T diag(w J) v'_q; v~' = V_h v'_h;
+//   (FP64); v'_h = Minv_k V_q^T diag(w J) v'_q (Minv_k the stored inverse, or the
+//   weight-adjusted one); v~' = V_h v'_h;
 //   H~ - Href = (v~1' + |v~23|^2/2)/g, h~ = Href + (H~ - Href) - b~ (FP64).
 // Subtracting the constant g Href is exact: the projection reproduces constants.
-template <typename real, int N, int CM>
+template <typename real, int N, int CM, bool WADG>
 __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L, real *out,
                                              real *nbx_out, int32_t *flag, bool coherent, int res = 0) {
   const bool to_records = (res & kResident) && !(res & kResLast);
@@ -267,19 +308,27 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
     L.T[i] = ya + yb;
   }
   __syncthreads();
-  // v'_h = Minv_k y
+  // v'_h = Minv_k y (weight-adjusted: the first factor into L.Q, dead once y is formed)
+  if constexpr (WADG) {
+    wadg_first<real, N>(ne, L, L.T, L.Q);
+    __syncthreads();
+  }
   for (int i = tid; i < 3 * ne * Np; i += nth) {
     const int c = (i >= ne * Np) + (i >= 2 * ne * Np), r = i - c * ne * Np, e = r / Np, row = r - e * Np;
-    const real *Mi = L.Minv + (e * Np + row) * Np;
-    const real *Tc = L.T + c * ne * Np + e * Np;
-    real va = 0, vb = 0;
+    if constexpr (WADG) {
+      L.VH[i] = wadg_second<real, N>(L, L.Q + c * ne * Nq + e * Nq, row);
+    } else {
+      const real *Mi = L.Minv + (e * Np + row) * Np;
+      const real *Tc = L.T + c * ne * Np + e * Np;
+      real va = 0, vb = 0;
 #pragma unroll 4
-    for (int j = 0; j + 1 < Np; j += 2) {
-      va += Mi[j] * Tc[j];
-      vb += Mi[j + 1] * Tc[j + 1];
+      for (int j = 0; j + 1 < Np; j += 2) {
+        va += Mi[j] * Tc[j];
+        vb += Mi[j + 1] * Tc[j + 1];
+      }
+      if (Np & 1) va += Mi[Np - 1] * Tc[Np - 1];
+      L.VH[i] = va + vb;
     }
-    if (Np & 1) va += Mi[Np - 1] * Tc[Np - 1];
-    L.VH[i] = va + vb;
   }
   __syncthreads();
   if constexpr (CM != kValu) {
@@ -375,7 +424,7 @@ __device__ __forceinline__ int stat_head(int nstat) {
 }
 
 // Phase 0: fetch the tile's global data into LDS (all asynchronous; see above).
-template <typename real, int N>
+template <typename real, int N, bool WADG>
 __device__ __forceinline__ void fetch_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, Lds<real, N> &L) {
   constexpr int Np = dim_Np(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
   constexpr int W = sizeof(real) / 4;     // 32-bit words per value
@@ -401,11 +450,12 @@ __device__ __forceinline__ void fetch_tile(const StageArgs &a, const InstDesc &d
       async_copy_words(lwords(L.U + c * ne * Np), words(src + c * splane + size_t(k0) * Np), ne * Np * W);
   }
   {
-    // static block (Minv, w J, b, push targets): contiguous in HBM and in LDS.  A stage
-    // copies only the part beyond the first kStatRegs * kBlock words here; that head goes
-    // through registers and lands in LDS after the residual (stage_tile).
-    const int nstat = ne * stat_words(N) * W, head = a.mode == kProject ? 0 : stat_head<real>(nstat);
-    async_copy_words(lwords(L.Minv) + head, words(static_cast<const real *>(d.stat) + size_t(k0) * stat_words(N)) + head,
+    // static block (mass data, w J, b, push targets): contiguous in HBM and in LDS.  A
+    // stage copies only the part beyond the first kStatRegs * kBlock words here; that head
+    // goes through registers and lands in LDS after the residual (stage_tile).
+    constexpr int SW = stat_words(N, WADG);
+    const int nstat = ne * SW * W, head = a.mode == kProject ? 0 : stat_head<real>(nstat);
+    async_copy_words(lwords(L.Minv) + head, words(static_cast<const real *>(d.stat) + size_t(k0) * SW) + head,
                      nstat - head);
   }
   if (a.mode != kProject) {        // neighbour values, pushed here by the neighbours' projections
@@ -607,24 +657,25 @@ __device__ __forceinline__ void interface_tile(const InstDesc &d, int ne, Lds<re
   }
 }
 
-template <typename real, int N, int R, int CM>
+template <typename real, int N, int R, int CM, bool WADG>
 __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm, real *tile,
                                            int res = 0, int t = 0, int target = 0) {
   constexpr int Np = dim_Np(N), Nh = dim_Nh(N), Nfq = dim_Nfq(N);
   const int tid = phase_tid(), nth = blockDim.x;
-  Lds<real, N> L(sm, tile, ne);
+  constexpr int Nq = dim_Nq(N);
+  Lds<real, N> L(sm, tile, ne, mass_words(N, WADG));
   const real g = real(d.g);
   const bool mid = res & kResMid;                // resident tile after its first stage
   const bool keep = (res & kResident) && !(res & kResLast);   // state stays in LDS only
   // a resident tile after its first stage has everything but the neighbour values in LDS;
   // it fetches those after the pair loop, once its neighbours have pushed them
-  if (!mid) fetch_tile<real, N>(a, d, k0, ne, L);
+  if (!mid) fetch_tile<real, N, WADG>(a, d, k0, ne, L);
   // head of the static block: loaded into registers now, while the node records and the
   // residual run, and written to LDS before the barrier that ends the residual
   constexpr int W = sizeof(real) / 4;
-  const int nstat = ne * stat_words(N) * W, head = stat_head<real>(nstat);
+  const int nstat = ne * stat_words(N, WADG) * W, head = stat_head<real>(nstat);
   constexpr int SR = StatRegs<real>::value;
-  const uint32_t *sg = static_cast<const uint32_t *>(d.stat) + size_t(k0) * stat_words(N) * W;
+  const uint32_t *sg = static_cast<const uint32_t *>(d.stat) + size_t(k0) * stat_words(N, WADG) * W;
   uint32_t sreg[SR];
   if (a.mode != kProject && !mid) {
 #pragma unroll
@@ -635,7 +686,7 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
   }
   if (a.mode == kProject) {
     __syncthreads();
-    project_tile<real, N, CM>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]),
+    project_tile<real, N, CM, WADG>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]),
                               static_cast<real *>(d.nbx[a.out_buf]), a.flag, a.progress != nullptr);
     return true;
   }
@@ -700,19 +751,28 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
   real *du = static_cast<real *>(d.du);
   real *rhs_out = static_cast<real *>(a.ext_rhs);
   const real ra = real(a.rk_a), rdt = real(d.dt), rb = real(a.rk_b);
+  if constexpr (WADG) {            // first factor into the residual block (dead after the lift)
+    wadg_first<real, N>(ne, L, L.T, L.R);
+    __syncthreads();
+  }
   // one task per (field, element, mode)
   for (int i = tid; i < 3 * ne * Np; i += nth) {
     const int c = (i >= ne * Np) + (i >= 2 * ne * Np), j = i - c * ne * Np, e = j / Np, row = j - e * Np;
-    const real *Mi = L.Minv + (e * Np + row) * Np;
-    const real *Tc = L.T + c * ne * Np + e * Np;
-    real ra0 = 0, ra1 = 0;
+    real rr;
+    if constexpr (WADG) {
+      rr = -wadg_second<real, N>(L, L.R + c * ne * Nq + e * Nq, row);
+    } else {
+      const real *Mi = L.Minv + (e * Np + row) * Np;
+      const real *Tc = L.T + c * ne * Np + e * Np;
+      real ra0 = 0, ra1 = 0;
 #pragma unroll 4
-    for (int m = 0; m + 1 < Np; m += 2) {
-      ra0 -= Mi[m] * Tc[m];
-      ra1 -= Mi[m + 1] * Tc[m + 1];
+      for (int m = 0; m + 1 < Np; m += 2) {
+        ra0 -= Mi[m] * Tc[m];
+        ra1 -= Mi[m + 1] * Tc[m + 1];
+      }
+      if (Np & 1) ra0 -= Mi[Np - 1] * Tc[Np - 1];
+      rr = ra0 + ra1;
     }
-    if (Np & 1) ra0 -= Mi[Np - 1] * Tc[Np - 1];
-    const real rr = ra0 + ra1;
     const size_t o = size_t(c) * splane + size_t(k0) * Np + j;
     if (a.mode == kRhs) {
       rhs_out[o] = rr;
@@ -729,7 +789,7 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
   }
   if (a.mode == kStage) {
     __syncthreads();
-    project_tile<real, N, CM>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]),
+    project_tile<real, N, CM, WADG>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]),
                               static_cast<real *>(d.nbx[a.out_buf]), a.flag, a.progress != nullptr, res);
   }
   return true;
@@ -746,7 +806,7 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
 // tiles have finished the previous one (see wait_neighbours), which the co-residency of
 // all workgroups (cooperative launch) makes safe.  A wait that gives up sets flag bit 1
 // and ends the workgroup; its neighbours' waits then give up in turn.
-template <typename real, int CM>
+template <typename real, int CM, bool WADG>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel(StageArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -790,11 +850,11 @@ stage_kernel(StageArgs a) {
       }
       bool ok = true;
       switch (d.N) {
-        case 1: ok = stage_tile<real, 1, RowsPerThread<real, 1>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
-        case 2: ok = stage_tile<real, 2, RowsPerThread<real, 2>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
-        case 3: ok = stage_tile<real, 3, RowsPerThread<real, 3>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
-        case 4: ok = stage_tile<real, 4, RowsPerThread<real, 4>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
-        case 5: ok = stage_tile<real, 5, RowsPerThread<real, 5>::value, CM>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
+        case 1: ok = stage_tile<real, 1, RowsPerThread<real, 1>::value, CM, WADG>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
+        case 2: ok = stage_tile<real, 2, RowsPerThread<real, 2>::value, CM, WADG>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
+        case 3: ok = stage_tile<real, 3, RowsPerThread<real, 3>::value, CM, WADG>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
+        case 4: ok = stage_tile<real, 4, RowsPerThread<real, 4>::value, CM, WADG>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
+        case 5: ok = stage_tile<real, 5, RowsPerThread<real, 5>::value, CM, WADG>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
         default: break;
       }
       if (!ok) {
@@ -870,23 +930,28 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagArgs a) {
 
 // ---------------------------------------------------------------- host launchers
 
-static const void *stage_fn(bool fp64, int cm) {
+template <bool WADG>
+static const void *stage_fn_mass(bool fp64, int cm) {
   if (fp64)
-    return cm == kMfmaNative ? reinterpret_cast<const void *>(&stage_kernel<double, kMfmaNative>)
-                             : reinterpret_cast<const void *>(&stage_kernel<double, kValu>);
-  if (cm == kMfmaBf16x3) return reinterpret_cast<const void *>(&stage_kernel<float, kMfmaBf16x3>);
-  if (cm == kMfmaNative) return reinterpret_cast<const void *>(&stage_kernel<float, kMfmaNative>);
-  return reinterpret_cast<const void *>(&stage_kernel<float, kValu>);
+    return cm == kMfmaNative ? reinterpret_cast<const void *>(&stage_kernel<double, kMfmaNative, WADG>)
+                             : reinterpret_cast<const void *>(&stage_kernel<double, kValu, WADG>);
+  if (cm == kMfmaBf16x3) return reinterpret_cast<const void *>(&stage_kernel<float, kMfmaBf16x3, WADG>);
+  if (cm == kMfmaNative) return reinterpret_cast<const void *>(&stage_kernel<float, kMfmaNative, WADG>);
+  return reinterpret_cast<const void *>(&stage_kernel<float, kValu, WADG>);
+}
+
+static const void *stage_fn(bool fp64, int cm, bool wadg) {
+  return wadg ? stage_fn_mass<true>(fp64, cm) : stage_fn_mass<false>(fp64, cm);
 }
 
 // Workgroups of the stage kernel that stay resident on the whole device.
-hipError_t stage_max_blocks(bool fp64, int cm, size_t lds_bytes, int *out) {
+hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, size_t lds_bytes, int *out) {
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_fn(fp64, cm), kBlock, lds_bytes);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_fn(fp64, cm, wadg), kBlock, lds_bytes);
   if (e != hipSuccess) return e;
   // The occupancy query does not round the LDS request up to the allocation granule; a
   // workgroup count it reports can then fail to fit, and the persistent grid's surplus
@@ -900,8 +965,8 @@ hipError_t stage_max_blocks(bool fp64, int cm, size_t lds_bytes, int *out) {
   return hipSuccess;
 }
 
-hipError_t set_stage_lds_limit(bool fp64, int cm, size_t lds_bytes) {
-  return hipFuncSetAttribute(stage_fn(fp64, cm), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
+hipError_t set_stage_lds_limit(bool fp64, int cm, bool wadg, size_t lds_bytes) {
+  return hipFuncSetAttribute(stage_fn(fp64, cm, wadg), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
 }
 
 // Persistent grid: at most max_blocks (what stays resident), at most one block per tile,
@@ -915,18 +980,10 @@ int stage_grid(int ntiles, int max_blocks) {
 hipError_t launch_stage(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream) {
   if (a.ntiles <= 0) return hipSuccess;
   const int grid = stage_grid(a.ntiles, max_blocks);
-  const int cm = a.contraction;
-  if (fp64 && cm == kMfmaNative)
-    hipLaunchKernelGGL((stage_kernel<double, kMfmaNative>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
-  else if (fp64)
-    hipLaunchKernelGGL((stage_kernel<double, kValu>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
-  else if (cm == kMfmaBf16x3)
-    hipLaunchKernelGGL((stage_kernel<float, kMfmaBf16x3>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
-  else if (cm == kMfmaNative)
-    hipLaunchKernelGGL((stage_kernel<float, kMfmaNative>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
-  else
-    hipLaunchKernelGGL((stage_kernel<float, kValu>), dim3(grid), dim3(kBlock), lds_bytes, stream, a);
-  return hipGetLastError();
+  StageArgs arg = a;
+  void *params[] = {&arg};
+  return hipLaunchKernel(stage_fn(fp64, a.contraction, a.wadg != 0), dim3(grid), dim3(kBlock), params, lds_bytes,
+                         stream);
 }
 
 // Multi-stage launch: every workgroup of the grid must be resident at once (tiles wait on
@@ -936,7 +993,8 @@ hipError_t launch_stage_fused(bool fp64, const StageArgs &a, int max_blocks, siz
   const int grid = stage_grid(a.ntiles, max_blocks);
   StageArgs arg = a;
   void *params[] = {&arg};
-  return hipLaunchCooperativeKernel(stage_fn(fp64, a.contraction), dim3(grid), dim3(kBlock), params, lds_bytes, stream);
+  return hipLaunchCooperativeKernel(stage_fn(fp64, a.contraction, a.wadg != 0), dim3(grid), dim3(kBlock), params,
+                                    lds_bytes, stream);
 }
 
 hipError_t launch_diag(bool fp64, const DiagArgs &a, hipStream_t stream) {

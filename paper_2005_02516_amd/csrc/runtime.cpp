@@ -18,10 +18,10 @@
 #include "host_setup.hpp"
 
 namespace esdg {
-hipError_t set_stage_lds_limit(bool fp64, int cm, size_t lds_bytes);
+hipError_t set_stage_lds_limit(bool fp64, int cm, bool wadg, size_t lds_bytes);
 hipError_t launch_stage(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream);
 hipError_t launch_stage_fused(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream);
-hipError_t stage_max_blocks(bool fp64, int cm, size_t lds_bytes, int *out);
+hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, size_t lds_bytes, int *out);
 int stage_grid(int ntiles, int max_blocks);
 hipError_t launch_diag(bool fp64, const DiagArgs &a, hipStream_t stream);
 }  // namespace esdg
@@ -43,11 +43,11 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Default elements per workgroup: as many as keep E*Nh <= 512 and the tile's LDS
 // <= 40 KiB (with the reference block, several workgroups stay resident per CU).
-int default_epb(int N, size_t word) {
+int default_epb(int N, size_t word, bool wadg) {
   int best = 1;
   for (int E = 1; E <= 64; E *= 2) {
     if (E * dim_Nh(N) > 512) break;
-    if (size_t(tile_words(N, E)) * word > 40 * 1024) break;
+    if (size_t(tile_words(N, E, wadg)) * word > 40 * 1024) break;
     best = E;
   }
   return best;
@@ -65,6 +65,7 @@ struct esdg_swe {
   bool fp64 = true;
   bool bf16x3 = false;
   int contraction = 0;             // 0 VALU, 1 matrix cores (bulk precision), 2 split-bf16
+  bool wadg = false;               // weight-adjusted mass inverse instead of stored inverses
   size_t word = 8;
   std::map<int, RefElem> refs;
   std::vector<InstanceHost> host;
@@ -168,6 +169,7 @@ StageArgs base_args(esdg_swe *s, int inst) {
   a.flag = s->dev<int32_t>(s->flag_off);
   a.ref_words_max = s->ref_max;   // a multiple of 4: node records stay 16-byte aligned
   a.contraction = s->contraction;
+  a.wadg = s->wadg ? 1 : 0;
   return a;
 }
 
@@ -245,7 +247,7 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
   *out = nullptr;
   if (opt->precision < ESDG_FP64 || opt->precision > ESDG_FP32_BF16X3 || opt->flux < 0 || opt->flux > 1 ||
       !(opt->g > 0.0) || opt->matrix_cores < 0 || opt->matrix_cores > 2 || opt->fused_steps < 0 ||
-      opt->fused_steps > 2) {
+      opt->fused_steps > 2 || opt->mass_inverse < 0 || opt->mass_inverse > 1) {
     g_init_error = "esdg_swe_init: option out of range";
     return ESDG_EINVAL;
   }
@@ -260,6 +262,7 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
   s->fp64 = opt->precision == ESDG_FP64;
   s->bf16x3 = opt->precision == ESDG_FP32_BF16X3;
   s->contraction = s->bf16x3 ? 2 : (opt->matrix_cores == 2 ? 1 : 0);
+  s->wadg = opt->mass_inverse == ESDG_MASS_WEIGHT_ADJUSTED;
   s->word = s->fp64 ? 8 : 4;
   s->host.resize(n_inst);
   for (int i = 0; i < n_inst; ++i) {
@@ -276,7 +279,7 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
         return ESDG_EINVAL;
       }
     }
-    std::string m = build_instance(s->refs[I.N], I.K, I.xg, I.yg, I.b, I.Lx, I.Ly, s->host[i]);
+    std::string m = build_instance(s->refs[I.N], I.K, I.xg, I.yg, I.b, I.Lx, I.Ly, s->host[i], !s->wadg);
     if (!m.empty()) {
       g_init_error = "instance " + std::to_string(i) + ": " + m;
       return ESDG_EMESH;
@@ -290,10 +293,10 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
   size_t tile = 0;
   for (auto &kv : s->refs) {
     const int N = kv.first;
-    int E = opt->elems_per_block[N] ? opt->elems_per_block[N] : default_epb(N, s->word);
+    int E = opt->elems_per_block[N] ? opt->elems_per_block[N] : default_epb(N, s->word, s->wadg);
     s->epb[N] = E;
     s->ref_max = std::max(s->ref_max, ref_words(N));
-    tile = std::max(tile, size_t(tile_words(N, E)));
+    tile = std::max(tile, size_t(tile_words(N, E, s->wadg)));
   }
   s->ref_max = (s->ref_max + 3) & ~3;
   size_t lds = (size_t(s->ref_max) + tile) * s->word;
@@ -350,7 +353,7 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
     f.geo = take(4 * K * Nh * w);
     f.wJq = take(K * Nq * w);
     f.bq = take(K * Nq * w);
-    f.stat = take(K * size_t(stat_words(N)) * w);
+    f.stat = take(K * size_t(stat_words(N, s->wadg)) * w);
     f.rhs = take(3 * K * Np * w);
   }
   s->tiles_off = take(s->tiles.size() * sizeof(Tile));
@@ -376,11 +379,11 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
   s->ws = static_cast<unsigned char *>(dev_workspace);
   s->stream = static_cast<hipStream_t>(hip_stream);
   if (s->lds_bytes > 64 * 1024) {
-    hipError_t e = set_stage_lds_limit(s->fp64, s->contraction, s->lds_bytes);
+    hipError_t e = set_stage_lds_limit(s->fp64, s->contraction, s->wadg, s->lds_bytes);
     if (e != hipSuccess) return s->hip_fail(e, "hipFuncSetAttribute (LDS)");
   }
   {
-    hipError_t e = stage_max_blocks(s->fp64, s->contraction, s->lds_bytes, &s->max_blocks);
+    hipError_t e = stage_max_blocks(s->fp64, s->contraction, s->wadg, s->lds_bytes, &s->max_blocks);
     if (e != hipSuccess) return s->hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (std::getenv("ESDG_SWE_VERBOSE")) {
       std::fprintf(stderr, "esdg_swe: %s, LDS %zu B per workgroup, %d resident workgroups, %zu tiles;",
@@ -430,8 +433,8 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
         if (p < 0 || size_t(p) >= push.size() || hit[p]) return s->fail(ESDG_EMESH, "face push map is not a permutation");
         hit[p] = 1;
       }
-      // static blocks in tile order (the layout of the tile's LDS region from Minv on)
-      const size_t SW = size_t(stat_words(H.N)), word = s->word;
+      // static blocks in tile order (the layout of the tile's LDS region from the mass data on)
+      const size_t SW = size_t(stat_words(H.N, s->wadg)), word = s->word;
       std::vector<unsigned char> blk(size_t(H.K) * SW * word, 0);
       auto put = [&](size_t real_index, double v) {
         if (s->fp64) std::memcpy(&blk[real_index * 8], &v, 8);
@@ -440,8 +443,13 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
       for (int t = s->tile_begin[i]; t < s->tile_begin[i] + s->tile_count[i]; ++t) {
         const int k0 = s->tiles[t].k0, ne = s->tiles[t].ne;
         size_t o = size_t(k0) * SW;
-        for (int e = 0; e < ne; ++e)
-          for (int j = 0; j < Np * Np; ++j) put(o++, H.Minv[size_t(k0 + e) * Np * Np + j]);
+        if (s->wadg) {             // w/J at the volume nodes
+          for (int e = 0; e < ne; ++e)
+            for (int q = 0; q < Nq; ++q) put(o++, H.wOverJ[size_t(k0 + e) * Nq + q]);
+        } else {                   // the stored inverse curved mass matrices
+          for (int e = 0; e < ne; ++e)
+            for (int j = 0; j < Np * Np; ++j) put(o++, H.Minv[size_t(k0 + e) * Np * Np + j]);
+        }
         for (int e = 0; e < ne; ++e)
           for (int q = 0; q < Nq; ++q) put(o++, H.wJq[size_t(k0 + e) * Nq + q]);
         for (int e = 0; e < ne; ++e)

@@ -8,6 +8,9 @@ lift with absolute values:
 
     bound = |M_h^-1| |V_h^T| ( sum_n 2 (|Qx_mn| |Fx_mn| + |Qy_mn| |Fy_mn|) + |source| + |interface| )
 
+(with the weight-adjusted mass inverse, |M_h^-1| is replaced by its factored form
+|V_q^T| diag(w/J) |V_q|).
+
 A result within c * eps * bound (c of order the accumulation length) is as accurate as
 the arithmetic allows.  Built from oracle quantities only.
 """
@@ -42,6 +45,8 @@ def rhs_abs_bound(o: "O.Oracle", uh: np.ndarray, ks: np.ndarray) -> np.ndarray:
                                         nJy * (np.abs(fS_y[c]) + np.abs(f_y[c])) +
                                         0.5 * lam * sJ * (np.abs(up[c]) + np.abs(uf[c])))
     y = r @ np.abs(ref.Vh)                                     # [3, k, Np]
+    if d.mass == "wadg":                                       # |V_q|^T diag(w/J) |V_q| (M = I)
+        return ((y @ np.abs(ref.Vq).T) * d.w_over_J[ks]) @ np.abs(ref.Vq)
     Minv = np.abs(np.linalg.inv(d.Mh[ks]))                     # [k, Np, Np]
     return np.einsum("kij,ckj->cki", Minv, y)
 

@@ -84,3 +84,28 @@ def test_calls_before_bind_fail_cleanly():
     u = np.ascontiguousarray(w.u_nodes)
     assert lib.esdg_swe_set_state(h, 0, binding._dptr(u)) == binding.ESDG_ESTATE
     lib.esdg_swe_destroy(h)
+
+
+def test_init_weight_adjusted_mass():
+    """ESDG_MASS_WEIGHT_ADJUSTED plans without a device, stores Nq reals of w/J per element
+    instead of the Np x Np inverse (smaller workspace), and an unknown mode is rejected."""
+    lib = binding.load_library()
+    w = wl.config2(n=3, N=5)
+    sizes = {}
+    for mass in ("stored", "wadg"):
+        xg, yg, b = (np.ascontiguousarray(a) for a in (w.xg, w.yg, w.b_nodes))
+        arr = (binding.esdg_swe_instance * 1)()
+        arr[0] = binding.esdg_swe_instance(w.N, w.K, binding._dptr(xg), binding._dptr(yg), binding._dptr(b), w.Lx, w.Ly)
+        opt = binding.make_options("fp32", "lf", 1.0, True, 0, mass=mass)
+        h, nb = C.c_void_p(), C.c_size_t()
+        assert lib.esdg_swe_init(1, arr, C.byref(opt), C.byref(h), C.byref(nb)) == binding.ESDG_OK
+        sizes[mass] = nb.value
+        lib.esdg_swe_destroy(h)
+    Np, Nq = 21, 36
+    assert sizes["stored"] - sizes["wadg"] >= 4 * w.K * (Np * Np - Nq)
+    opt = binding.make_options("fp32", "lf", 1.0, True, 0)
+    opt.mass_inverse = 2
+    arr = (binding.esdg_swe_instance * 1)()
+    arr[0] = binding.esdg_swe_instance(w.N, w.K, binding._dptr(xg), binding._dptr(yg), binding._dptr(b), w.Lx, w.Ly)
+    h, nb = C.c_void_p(), C.c_size_t()
+    assert lib.esdg_swe_init(1, arr, C.byref(opt), C.byref(h), C.byref(nb)) == binding.ESDG_EINVAL
