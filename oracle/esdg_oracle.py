@@ -312,10 +312,11 @@ class Discretization:
     def _connect(self) -> np.ndarray:
         """mapP[k, f]: flat index k'*Nfq + f' of the neighbour's face node at the same point.
 
-        Faces are paired by the periodic images of their midpoints (rounded to a fine grid,
-        then wrapped); the nodes of two paired faces are matched by nearest periodic
-        distance.  Every face must have exactly one partner and every node a partner
-        closer than the tolerance.
+        Faces are paired by their midpoints (rounded to a fine grid; wrapped by the period in
+        each periodic direction, a period <= 0 meaning none); the nodes of two paired faces are
+        matched by nearest distance (periodic where periodic).  A face whose midpoint no other
+        face shares is a reflective wall (Section 2.9) when some direction is not periodic,
+        and an error otherwise; its nodes map to themselves and are marked in self.wall.
         """
         ref = self.ref
         K, Nfp, Nq = self.K, ref.Nfp, ref.Nq
@@ -324,28 +325,46 @@ class Discretization:
         hscale = float(np.max(np.hypot(xf[:, -1] - xf[:, 0], yf[:, -1] - yf[:, 0])))
         tol = 1e-7 * hscale
         cell = 1e-4 * hscale
-        ncx = int(round(self.Lx / cell))
-        ncy = int(round(self.Ly / cell))
-        kx = np.round((xf.mean(axis=1) % self.Lx) / cell).astype(np.int64) % ncx
-        ky = np.round((yf.mean(axis=1) % self.Ly) / cell).astype(np.int64) % ncy
-        key = kx * ncy + ky
+        px, py = self.Lx > 0, self.Ly > 0
+        mx, my = xf.mean(axis=1), yf.mean(axis=1)
+        if px:
+            mx = mx % self.Lx
+        if py:
+            my = my % self.Ly
+        kx = np.round(mx / cell).astype(np.int64)
+        ky = np.round(my / cell).astype(np.int64)
+        if px:
+            kx %= int(round(self.Lx / cell))
+        if py:
+            ky %= int(round(self.Ly / cell))
+        key = (kx - kx.min()) * (int(ky.max() - ky.min()) + 1) + (ky - ky.min())
+        uniq, inverse, counts = np.unique(key, return_inverse=True, return_counts=True)
+        if np.any(counts > 2):
+            raise ValueError("more than two faces share a midpoint")
+        single = counts[inverse] == 1
+        if np.any(single) and px and py:
+            raise ValueError("every face needs exactly one periodic partner")
+        partner = np.arange(K * 3)
         order = np.argsort(key, kind="stable")
         ks = key[order]
-        if ks.size % 2 or np.any(ks[0::2] != ks[1::2]) or (ks.size > 2 and np.any(ks[2::2] == ks[1:-1:2])):
-            raise ValueError("every face needs exactly one periodic partner")
-        partner = np.empty(K * 3, dtype=np.int64)
-        partner[order[0::2]] = order[1::2]
-        partner[order[1::2]] = order[0::2]
-        # node matching: nearest node of the partner face, distances taken periodically
+        first = np.nonzero(np.r_[True, ks[1:] != ks[:-1]])[0]
+        for a in first:
+            if a + 1 < ks.size and ks[a + 1] == ks[a]:
+                partner[order[a]], partner[order[a + 1]] = order[a + 1], order[a]
+        # node matching: nearest node of the partner face (distances periodic where periodic)
         dx = xf[partner][:, None, :] - xf[:, :, None]
         dy = yf[partner][:, None, :] - yf[:, :, None]
-        dx -= self.Lx * np.round(dx / self.Lx)
-        dy -= self.Ly * np.round(dy / self.Ly)
+        if px:
+            dx -= self.Lx * np.round(dx / self.Lx)
+        if py:
+            dy -= self.Ly * np.round(dy / self.Ly)
         d = np.hypot(dx, dy)                                 # [face, my node, partner node]
         j = np.argmin(d, axis=2)
+        j[single] = np.arange(Nfp)[None, :]                  # wall faces: each node itself
         if np.max(np.take_along_axis(d, j[:, :, None], axis=2)) > tol:
             raise ValueError("unmatched face node")
         mapP = partner[:, None] * Nfp + j                      # flat face-node index
+        self.wall = np.repeat(single, Nfp).reshape(K, 3 * Nfp)
         return mapP.reshape(K, 3 * Nfp)
 
     # -- nodal <-> modal --------------------------------------------------------------
@@ -423,6 +442,23 @@ def conservative_from_entropy(v1, v2, v3, b, g):
     """Inverse map of entropy_variables: h = (v1 + (v2^2 + v3^2)/2)/g - b, hu = h v2, hv = h v3."""
     h = (v1 + 0.5 * (v2 * v2 + v3 * v3)) / g - b
     return h, h * v2, h * v3
+
+
+def exterior_state(d: "Discretization", ut: np.ndarray, ks: np.ndarray) -> np.ndarray:
+    """u~+ at the face nodes of elements ks, shape [3, len(ks), Nfq]: the neighbour's value at
+    the matching node, or on a reflective wall (Section 2.9) the mirror state h+ = h,
+    (hu, hv)+ = (hu, hv) - 2 ((hu, hv) . n) n with n the unit outward normal."""
+    Nq = d.ref.Nq
+    up = ut[:, :, Nq:].reshape(3, -1)[:, d.mapP[ks].reshape(-1)].reshape(3, ks.size, d.ref.Nfq).copy()
+    w = d.wall[ks]
+    if np.any(w):
+        nx, ny = d.nJx[ks] / d.sJ[ks], d.nJy[ks] / d.sJ[ks]
+        h, hu, hv = ut[0, ks, Nq:], ut[1, ks, Nq:], ut[2, ks, Nq:]
+        mn = hu * nx + hv * ny
+        up[0][w] = h[w]
+        up[1][w] = (hu - 2.0 * mn * nx)[w]
+        up[2][w] = (hv - 2.0 * mn * ny)[w]
+    return up
 
 
 def physical_flux(h, hu, hv, g):
@@ -530,7 +566,7 @@ class Oracle:
             r[2, sel] += g * ut[0, ks] * np.einsum("kmn,kn->km", Qy, bt)
         # interface terms on the face rows
         uf = ut[:, ks_all, Nq:]                                   # [3,k,Nfq]
-        up = ut[:, :, Nq:].reshape(3, -1)[:, d.mapP[ks_all].reshape(-1)].reshape(uf.shape)
+        up = exterior_state(d, ut, ks_all)
         fS_x, fS_y = ec_flux(tuple(up), tuple(uf), g)
         f_x, f_y = physical_flux(uf[0], uf[1], uf[2], g)
         wf = ref.wf[None, :]

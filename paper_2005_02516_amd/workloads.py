@@ -37,6 +37,8 @@ __all__ = [
     "config3",
     "config4_instances",
     "config5",
+    "basin",
+    "basin_mesh",
     "vortex_fields",
     "make_config",
 ]
@@ -117,6 +119,30 @@ def structured_mesh(n: int, N: int, L: float = 2.0, warp: float = 0.0, x0: float
     return xg, yg, xf, yf
 
 
+def basin_mesh(n: int, N: int, wall: float = 0.15, warp: float = 0.05):
+    """Closed basin: the image of [0,2]^2 under
+    x' = x + wall sin(pi y / 2)(1 - x / 2) + d,  y' = y + wall sin(pi x / 2)(1 - y / 2) + d,
+    d = warp sin(pi x) sin(pi y), all evaluated at the unwarped lattice position.  The left
+    (x = 0) and bottom (y = 0) walls bulge into the domain along sin(pi s / 2); the right and
+    top walls stay straight; d vanishes on the boundary.  Same triangulation and node order
+    as structured_mesh; no periodic images (xf, yf are the node positions themselves).
+    Returns (xg, yg)."""
+    ij = equispaced_index(N)
+    M = n * N
+    hl = 2.0 / M
+    jq, iq = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    bi = (iq.reshape(-1) * N)[:, None]
+    bj = (jq.reshape(-1) * N)[:, None]
+    i_, j_ = ij[None, :, 0], ij[None, :, 1]
+    I = np.stack([bi + i_ + j_, bi + i_], axis=1).reshape(-1, ij.shape[0]).astype(np.float64)
+    J = np.stack([bj + j_, bj + i_ + j_], axis=1).reshape(-1, ij.shape[0]).astype(np.float64)
+    x, y = I * hl, J * hl
+    d = warp * np.sin(np.pi * x) * np.sin(np.pi * y)
+    xg = x + wall * np.sin(0.5 * np.pi * y) * (1.0 - 0.5 * x) + d
+    yg = y + wall * np.sin(0.5 * np.pi * x) * (1.0 - 0.5 * y) + d
+    return xg, yg
+
+
 def timestep(u_nodes: np.ndarray, g: float, N: int, hmesh: float, cfl: float) -> float:
     """dt = CFL * hmesh / (C_N * a_max), C_N = (N+1)(N+2)/2 (Section 4), a_max = max |u| + sqrt(g h)."""
     h = u_nodes[0]
@@ -164,6 +190,25 @@ def config2(n: int = 64, N: int = 3, seed: int = 0, bump: float = 0.01, steps: i
     z = np.zeros_like(h)
     return _mk("config2", n, N, 0.05, 1.0, b, h, z, z.copy(), "lf", 0.25, steps, "fp32", seed, xg, yg, xf, yf,
                meta={"center": (float(cx), float(cy)), "H": 2.2})
+
+
+def basin(n: int = 64, N: int = 3, wall: float = 0.15, dam: float = 0.2, width: float = 0.1,
+          steps: int = 200) -> Workload:
+    """Reflective-wall case (Section 2.9) on a boundary-fitted curved mesh: the closed basin of
+    basin_mesh (periods 0: not periodic, every boundary face a wall) over
+    b = 0.1 + 0.05 cos(pi x / 2) cos(pi y / 2), still water whose free surface steps down
+    smoothly across x = 1 (a dam-break-like start): h + b = 1.2 + dam (1 - tanh((x - 1) /
+    width)) / 2, u = v = 0, LF flux."""
+    xg, yg = basin_mesh(n, N, wall=wall)
+    b = 0.1 + 0.05 * np.cos(0.5 * np.pi * xg) * np.cos(0.5 * np.pi * yg)
+    h = 1.2 + dam * 0.5 * (1.0 - np.tanh((xg - 1.0) / width)) - b
+    z = np.zeros_like(h)
+    u = np.ascontiguousarray(np.stack([h, z, z.copy()]))
+    w = Workload(name="basin", N=N, n=n, K=xg.shape[0], xg=xg, yg=yg, xf=xg, yf=yg, Lx=0.0, Ly=0.0, g=1.0,
+                 b_nodes=np.ascontiguousarray(b), u_nodes=u, flux="lf", cfl=0.25, steps=steps, precision="fp32",
+                 seed=0, meta={"walls": True})
+    w.dt = timestep(u, w.g, N, 2.0 / n, w.cfl)
+    return w
 
 
 def _fourier(rng, x, y, nmodes, amax, kmax=4):

@@ -34,7 +34,7 @@ def rhs_abs_bound(o: "O.Oracle", uh: np.ndarray, ks: np.ndarray) -> np.ndarray:
     r[1] += g * np.abs(ut[0, ks]) * np.einsum("kmn,kn->km", np.abs(Qx), bt)
     r[2] += g * np.abs(ut[0, ks]) * np.einsum("kmn,kn->km", np.abs(Qy), bt)
     uf = ut[:, ks, Nq:]
-    up = ut[:, :, Nq:].reshape(3, -1)[:, d.mapP[ks].reshape(-1)].reshape(uf.shape)
+    up = O.exterior_state(d, ut, ks)
     fS_x, fS_y = O.ec_flux(tuple(up), tuple(uf), g)
     f_x, f_y = O.physical_flux(uf[0], uf[1], uf[2], g)
     nJx, nJy, sJ = np.abs(d.nJx[ks]), np.abs(d.nJy[ks]), d.sJ[ks]
