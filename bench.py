@@ -196,6 +196,8 @@ def main():
                     help="per-stage: one launch per RK stage (graph replays); fused: all stages of a step "
                          "call in one cooperative launch with neighbour-tile waits; auto (default): fused "
                          "when every workgroup holds one tile, which then stays in LDS")
+    ap.add_argument("--walls", action="store_true",
+                    help="the closed curved-wall basin (reflective walls) instead of the periodic workload")
     ap.add_argument("--mass", choices=["stored", "wadg"], default="stored",
                     help="inverse curved mass matrices: stored per element (default), or the "
                          "weight-adjusted inverse (w/J per volume node)")
@@ -226,7 +228,7 @@ def main():
 
     if args.ensemble:
         return ensemble(args, torch)
-    w = wl.config2(n=args.n, N=args.N)
+    w = wl.basin(n=args.n, N=args.N) if args.walls else wl.config2(n=args.n, N=args.N)
     Np, Nq, Nfq, Nh = dims(w.N)
     dof = w.K * Np
     print(f"# workload: K={w.K} N={w.N} Np={Np} DOF={dof} dt={w.dt:.4e}", file=sys.stderr, flush=True)
@@ -268,7 +270,7 @@ def main():
     frac_hbm = achieved_gbs / PEAK_HBM_GBS
     step_mode = plans[prec]["step_mode"]
     stages_per_launch = 1 if step_mode == 0 else 5 * args.steps
-    tr = None if wadg else measured_traffic(w, prec, epb_used.get(prec, 0), step_mode, stages_per_launch)
+    tr = None if (wadg or args.walls) else measured_traffic(w, prec, epb_used.get(prec, 0), step_mode, stages_per_launch)
     # which roof binds: with measured traffic, the HBM side is what the kernel really moves
     # (tiles resident in LDS move far less than the algorithmic bytes); else the larger of
     # the two algorithmic fractions
@@ -309,7 +311,9 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "f32 (bf16x3 contractions)"}[prec],
         "data": "synthetic",
-        "config": {"workload": f"curved periodic lake at rest + Gaussian bump, {args.n}x{args.n}x2={w.K} triangles, "
+        "config": {"workload": (f"closed curved-wall basin (reflective walls), smoothed dam-break start, "
+                                if args.walls else "curved periodic lake at rest + Gaussian bump, ") +
+                               f"{args.n}x{args.n}x2={w.K} triangles, "
                                f"N={w.N} (Np={Np}, Nq={Nq}, Nfq={Nfq}), LF flux, LSRK4(5)",
                    "K": w.K, "N": w.N, "DOF": dof, "precision": prec, "hip_graph": not args.no_graph,
                    "elements_per_workgroup": epb_used.get(prec, 0),

@@ -102,7 +102,8 @@ enum {
                                      conserved only to the accuracy of the weight adjustment. */
 };
 
-/* One independent shallow-water instance on a periodic box. */
+/* One independent shallow-water instance on a periodic box, or a domain closed (in one or
+ * both directions) by reflective walls. */
 typedef struct {
   int32_t N;            /* polynomial (and geometry) degree, 1..5                          */
   int32_t K;            /* number of triangles, >= 1                                        */
@@ -110,8 +111,13 @@ typedef struct {
   const double *yg;     /* [K][Np] y of the same nodes; each element counter-clockwise      */
   const double *b;      /* [K][Np] bathymetry sampled at the same nodes (C0 across faces for
                            the well-balanced property); NULL means b = 0                     */
-  double Lx, Ly;        /* periods in x and y: every face must match a face of another
-                           element, possibly shifted by a multiple of (Lx, Ly)              */
+  double Lx, Ly;        /* periods in x and y; a period <= 0 means the mesh is not periodic
+                           in that direction.  Every face must match a face of another
+                           element (shifted by a multiple of the period in each periodic
+                           direction), except that, when some direction is not periodic, a
+                           face no other face matches is a reflective wall (Section 2.9):
+                           its exterior state is the interior one with the normal velocity
+                           reversed, h+ = h, (u, v)+ = (u, v) - 2 ((u, v) . n) n            */
 } esdg_swe_instance;
 
 typedef struct {
@@ -139,9 +145,10 @@ typedef struct {
 
 /* Plan a solver for n_inst independent instances (n_inst = 1 for a single run).  Builds,
  * on the host in double precision, the reference operators of each degree, the
- * isoparametric geometry, the periodic face connectivity and the inverse curved mass
- * matrices, or with ESDG_MASS_WEIGHT_ADJUSTED the weights w/J (Sections 2.1-2.7).  Validates: 1 <= N <= 5, J > 0 at every quadrature node,
- * every face node matched.  On success *out is a new handle and *workspace_bytes the
+ * isoparametric geometry, the face connectivity (periodic, or reflective walls) and the
+ * inverse curved mass matrices, or with ESDG_MASS_WEIGHT_ADJUSTED the weights w/J
+ * (Sections 2.1-2.7, 2.9).  Validates: 1 <= N <= 5, J > 0 at every quadrature node, every
+ * face node matched (or on a wall).  On success *out is a new handle and *workspace_bytes the
  * device workspace size esdg_swe_bind needs.  No device call is made. */
 esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const esdg_swe_options *opt,
                           esdg_swe **out, size_t *workspace_bytes);
@@ -186,8 +193,9 @@ esdg_status esdg_swe_step(esdg_swe *s, const double *dt, int32_t nsteps);
 
 /* Per-instance FP64 diagnostics of the current state, out = host [n_inst][6]:
  *   mass of h, hu, hv (sum_k 1^T W J V_q u_h), total entropy sum w J S(u_q) (Section 2.4),
- *   entropy rate sum w J v(u_q).(V_q du/dt) (zero for the EC flux on periodic meshes,
- *   <= 0 with LF), and the sum of the absolute values of the entropy-rate terms.
+ *   entropy rate sum w J v(u_q).(V_q du/dt) (zero for the EC flux on periodic or
+ *   wall-bounded meshes, <= 0 with LF), and the sum of the absolute values of the
+ *   entropy-rate terms.
  * Synchronises the stream. */
 esdg_status esdg_swe_diagnostics(esdg_swe *s, double *out);
 

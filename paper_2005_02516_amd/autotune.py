@@ -38,8 +38,47 @@ def _load() -> dict:
         return json.load(f)
 
 
+def ref_words(N: int) -> int:
+    """LDS reals of the reference block of degree N (rounded up to 4, as the library does)."""
+    Np, Nq, Nfq = (N + 1) * (N + 2) // 2, (N + 1) ** 2, 3 * (N + 1)
+    Nh = Nq + Nfq
+    return (Nh * Np + 2 * Nh * Nq + 2 * Nq * Nfq + 3 * Nfq + 3) // 4 * 4
+
+
+def tile_words(N: int, E: int) -> int:
+    """LDS reals of one tile of E elements of degree N (stored mass inverse)."""
+    Np, Nq, Nfq = (N + 1) * (N + 2) // 2, (N + 1) ** 2, 3 * (N + 1)
+    Nh = Nq + Nfq
+    return E * (Nh * 12 + 8 * Nh + 4 * Nfq + 6 * Np + Np * Np + 2 * Nq + Nh + Nfq)
+
+
+# LDS per workgroup at which four workgroups share a CU (160 KiB), the residency the stage
+# kernel's register budget allows
+LDS_FOUR_PER_CU = 40 * 1024
+
+
+def fit_mixed(precision: str, epb: Dict[int, int]) -> Dict[int, int]:
+    """One launch serves every degree with the LDS of the largest reference block plus the
+    largest tile, so a tile size tuned for a degree alone can lower the residency of all of
+    them.  Shrink each degree's E (through the candidate sizes) until the shared LDS fits
+    the larger of four workgroups per CU and what the degrees needed on their own."""
+    if len(epb) < 2:
+        return dict(epb)
+    word = 8 if precision == "fp64" else 4
+    ref_max = max(ref_words(N) for N in epb)
+    alone = max((ref_words(N) + tile_words(N, E)) * word for N, E in epb.items())
+    budget = max(LDS_FOUR_PER_CU, alone)
+    out = {}
+    for N, E in epb.items():
+        while E > 1 and (ref_max + tile_words(N, E)) * word > budget:
+            E = max(c for c in CANDIDATES if c < E)
+        out[N] = E
+    return out
+
+
 def lookup(precision: str, sizes: Iterable[Tuple[int, int]]) -> Optional[Dict[int, int]]:
-    """Tuned E per degree for instances of (N, K); the total K of each degree picks the class."""
+    """Tuned E per degree for instances of (N, K); the total K of each degree picks the class
+    (with several degrees, fitted to their shared LDS: fit_mixed)."""
     cache = _load().get("entries", {})
     totals: Dict[int, int] = {}
     for N, K in sizes:
@@ -54,7 +93,7 @@ def lookup(precision: str, sizes: Iterable[Tuple[int, int]]) -> Optional[Dict[in
             if e:
                 out[N] = int(e["epb"])
                 break
-    return out or None
+    return fit_mixed("fp32" if precision == "bf16x3" else precision, out) if out else None
 
 
 def time_config(w, precision: str, epb: int, steps: int = 4, warmup: int = 1) -> float:
@@ -78,12 +117,9 @@ def time_config(w, precision: str, epb: int, steps: int = 4, warmup: int = 1) ->
 
 
 def lds_ok(N: int, E: int, precision: str) -> bool:
-    Np, Nq, Nfq = (N + 1) * (N + 2) // 2, (N + 1) ** 2, 3 * (N + 1)
-    Nh = Nq + Nfq
-    ref = (Nh * Np + 2 * Nh * Nq + 2 * Nq * Nfq + 3 * Nfq + 3) // 4 * 4
-    tile = E * (Nh * 12 + 8 * Nh + 4 * Nfq + 6 * Np + Np * Np + 2 * Nq + Nh + Nfq)
+    Nh = (N + 1) ** 2 + 3 * (N + 1)
     word = 8 if precision == "fp64" else 4
-    return (ref + tile) * word <= 160 * 1024 and E * Nh <= 2048
+    return (ref_words(N) + tile_words(N, E)) * word <= 160 * 1024 and E * Nh <= 2048
 
 
 def tune(cases: List[Tuple[int, int]], precisions=("fp32", "fp64"), write: bool = True, log=sys.stderr):

@@ -12,6 +12,10 @@ constexpr int kNodeRec = 12;       // per hybrid node in LDS: hu/2 hv/2 u/2 v/2 
                                    // (three aligned quads, so a column is read with two 16-byte loads)
 constexpr int kXcds = 8;           // MI355X accelerator complex dies (each with its own L2)
 
+// Push-target flag: the face node lies on a reflective wall (Section 2.9); its projection
+// writes the mirror state into its own neighbour slot (the target's other bits).
+constexpr uint32_t kPushWall = 0x80000000u;
+
 __host__ __device__ constexpr int dim_Np(int N) { return (N + 1) * (N + 2) / 2; }
 __host__ __device__ constexpr int dim_Nq(int N) { return (N + 1) * (N + 1); }
 __host__ __device__ constexpr int dim_Nfq(int N) { return 3 * (N + 1); }
@@ -82,7 +86,8 @@ struct InstDesc {
                        // real k0 * stat_words(N, wadg): the mass data [ne][mass_words] (Minv
                        // [Np][Np], or w/J at the volume nodes [Nq]) | w J [ne][Nq] | b [ne][Nq] |
                        // b [ne][Nh] | push targets [ne][Nfq] (int32 k'*Nfq + f' of the nbx slot
-                       // that face node f fills, packed in the first ne*Nfq 32-bit words)
+                       // that face node f fills, packed in the first ne*Nfq 32-bit words;
+                       // kPushWall set on wall nodes, whose slot is their own)
   const void *ref;     // reference-operator block for this N
   void *rhs_scratch;   // [3][K][Np] used by the diagnostics
 };

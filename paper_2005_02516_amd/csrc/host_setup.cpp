@@ -374,12 +374,18 @@ std::string build_instance(const RefElem &R, int K, const double *xg, const doub
   }
   out.Jmin = Jmin; out.Jmax = Jmax;
 
-  // periodic face matching through quantised face midpoints
+  // face matching through quantised face midpoints, wrapped in each periodic direction (a
+  // period <= 0: none).  A face no other face matches is a reflective wall (Section 2.9)
+  // when some direction is not periodic; on a fully periodic box it is a mesh error.
+  const bool px = Lx > 0.0, py = Ly > 0.0;
   auto wrap = [](double v, double L) {
+    if (!(L > 0.0)) return v;
     double w = std::fmod(v, L);
     if (w < 0) w += L;
     return w;
   };
+  out.wall.assign(size_t(K) * Nfq, 0);
+  out.nwall = 0;
   double hmin = 1e300;
   std::vector<double> mx(size_t(K) * 3), my(size_t(K) * 3);
   for (int k = 0; k < K; ++k)
@@ -394,14 +400,15 @@ std::string build_instance(const RefElem &R, int K, const double *xg, const doub
       const size_t o0 = size_t(k) * Nh + Nq + f * Nfp, o1 = o0 + Nfp - 1;
       hmin = std::min(hmin, std::hypot(xh[o1] - xh[o0], yh[o1] - yh[o0]));
     }
-  const double tol = 1e-8 * std::max(Lx, Ly) + 1e-6 * hmin;
+  const double tol = 1e-8 * std::max(std::max(Lx, Ly), 0.0) + 1e-6 * hmin;
   const double cell = 4.0 * tol;
-  const int64_t ncx = std::max<int64_t>(1, int64_t(std::ceil(Lx / cell)));
-  const int64_t ncy = std::max<int64_t>(1, int64_t(std::ceil(Ly / cell)));
+  const int64_t ncx = px ? std::max<int64_t>(1, int64_t(std::ceil(Lx / cell))) : 0;
+  const int64_t ncy = py ? std::max<int64_t>(1, int64_t(std::ceil(Ly / cell))) : 0;
+  const int64_t kOff = int64_t(1) << 30;     // non-periodic cell indices: offset, then packed
   auto cell_key = [&](int64_t cx, int64_t cy) {
-    cx = ((cx % ncx) + ncx) % ncx;
-    cy = ((cy % ncy) + ncy) % ncy;
-    return cx * ncy + cy;
+    cx = px ? ((cx % ncx) + ncx) % ncx : cx + kOff;
+    cy = py ? ((cy % ncy) + ncy) % ncy : cy + kOff;
+    return cx * (int64_t(2) * kOff) + cy;
   };
   std::unordered_map<int64_t, std::vector<int>> grid;
   grid.reserve(size_t(K) * 3 * 2);
@@ -409,8 +416,8 @@ std::string build_instance(const RefElem &R, int K, const double *xg, const doub
     grid[cell_key(int64_t(std::floor(mx[e] / cell)), int64_t(std::floor(my[e] / cell)))].push_back(e);
   auto pdist = [&](double x1, double y1, double x2, double y2) {
     double dx = x2 - x1, dy = y2 - y1;
-    dx -= Lx * std::nearbyint(dx / Lx);
-    dy -= Ly * std::nearbyint(dy / Ly);
+    if (px) dx -= Lx * std::nearbyint(dx / Lx);
+    if (py) dy -= Ly * std::nearbyint(dy / Ly);
     return std::hypot(dx, dy);
   };
   for (int e = 0; e < 3 * K; ++e) {
@@ -426,9 +433,18 @@ std::string build_instance(const RefElem &R, int K, const double *xg, const doub
             partner = e2;
           }
       }
+    if (count == 0 && !(px && py)) {   // reflective wall: each node is its own exterior node
+      const int k = e / 3, f = e % 3;
+      for (int i = 0; i < Nfp; ++i) {
+        out.mapP[size_t(k) * Nfq + f * Nfp + i] = int32_t(size_t(k) * Nh + Nq + f * Nfp + i);
+        out.wall[size_t(k) * Nfq + f * Nfp + i] = 1;
+      }
+      out.nwall += Nfp;
+      continue;
+    }
     if (count != 1) {
-      std::snprintf(buf, sizeof buf, "face %d of element %d has %d periodic partners (need exactly 1)", e % 3, e / 3,
-                    count);
+      std::snprintf(buf, sizeof buf, "face %d of element %d has %d partners (need exactly 1%s)", e % 3, e / 3, count,
+                    px && py ? " on a fully periodic box" : "");
       return buf;
     }
     const int k = e / 3, f = e % 3, k2 = partner / 3, f2 = partner % 3;

@@ -49,6 +49,9 @@ struct InstanceHost {
   std::vector<double> bh;     // [K][Nh]: bathymetry at hybrid nodes
   std::vector<double> bmodal; // [K][Np]: modal coefficients of the bathymetry
   std::vector<int32_t> mapP;  // [K][Nfq]: k' * Nh + Nq + f' of the matching neighbour node
+                              // (the node itself on a reflective wall)
+  std::vector<uint8_t> wall;  // [K][Nfq]: 1 on reflective wall faces (Section 2.9)
+  long long nwall = 0;        // wall face nodes
   double Jmin = 0, Jmax = 0;
 };
 

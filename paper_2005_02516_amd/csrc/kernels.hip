@@ -372,24 +372,44 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
       out[3 * ne * Nh + o] = real(dH);
     }
     if (n >= Nq) {                 // face node: also fill the neighbour's face slot
-      real *slot = nbx_out + size_t(L.pp[e * Nfq + (n - Nq)]) * 4;
+      const int f = n - Nq;
+      const uint32_t tgt = uint32_t(L.pp[e * Nfq + f]);
+      real *slot = nbx_out + size_t(tgt & ~kPushWall) * 4;
+      double pu = v2, pv = v3;     // the velocity the exterior side of the face sees
+      if (tgt & kPushWall) {
+        // reflective wall (Section 2.9): the exterior state is this node's own with the
+        // normal velocity reversed, u+ = u - 2 (u . nJ) nJ / |nJ|^2, h+ = h (so H+ = H),
+        // written into this node's own slot; nJ from the metric factors (tile-blocked, as
+        // fetched) and the reference normal of the face
+        const real *gm = static_cast<const real *>(d.geo) + size_t(k0) * 4 * Nh + i;
+        const double nr = double(L.nr[f]), ns = double(L.ns[f]);
+        const double nx = double(gm[0]) * nr + double(gm[ne * Nh]) * ns;
+        const double ny = double(gm[2 * ne * Nh]) * nr + double(gm[3 * ne * Nh]) * ns;
+        const double c = 2.0 * (v2 * nx + v3 * ny) / (nx * nx + ny * ny);
+        pu = v2 - c * nx;
+        pv = v3 - c * ny;
+      }
       if (coherent) {
         // multi-stage launches: device-coherent (sc1) 16-byte vector stores, since the
         // neighbour's workgroup may sit on another XCD, whose L2 does not see this one's.
         // The slot is 16-byte aligned; publish() waits for these stores (vmcnt) itself.
+        // A vector store of more than 8 bytes reads its data registers after issue: a VALU
+        // write to them must wait two cycles.  The compiler inserts that wait only for stores
+        // it generates, not for these, so each statement carries its own s_nop (without it
+        // the FP64 pair below had its first store's data overwritten by the second's address).
         if constexpr (sizeof(real) == 4) {
           typedef float f4 __attribute__((ext_vector_type(4)));
-          const f4 val = {float(h), float(v2), float(v3), float(dH)};
-          asm volatile("global_store_dwordx4 %0, %1, off sc1" ::"v"(slot), "v"(val) : "memory");
+          const f4 val = {float(h), float(pu), float(pv), float(dH)};
+          asm volatile("global_store_dwordx4 %0, %1, off sc1\n\ts_nop 1" ::"v"(slot), "v"(val) : "memory");
         } else {
           typedef double d2 __attribute__((ext_vector_type(2)));
-          const d2 lo = {h, v2}, hi = {v3, dH};
-          asm volatile("global_store_dwordx4 %0, %1, off sc1" ::"v"(slot), "v"(lo) : "memory");
-          asm volatile("global_store_dwordx4 %0, %1, off sc1" ::"v"(slot + 2), "v"(hi) : "memory");
+          const d2 lo = {h, pu}, hi = {pv, dH};
+          asm volatile("global_store_dwordx4 %0, %1, off sc1\n\ts_nop 1" ::"v"(slot), "v"(lo) : "memory");
+          asm volatile("global_store_dwordx4 %0, %1, off sc1\n\ts_nop 1" ::"v"(slot + 2), "v"(hi) : "memory");
         }
       } else {
         typedef real real4 __attribute__((ext_vector_type(4)));
-        const real4 val = {real(h), real(v2), real(v3), real(dH)};
+        const real4 val = {real(h), real(pu), real(pv), real(dH)};
         *reinterpret_cast<real4 *>(slot) = val;
       }
     }

@@ -267,7 +267,7 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
   s->host.resize(n_inst);
   for (int i = 0; i < n_inst; ++i) {
     const esdg_swe_instance &I = inst[i];
-    if (I.N < 1 || I.N > kMaxN || I.K < 1 || !I.xg || !I.yg || !(I.Lx > 0) || !(I.Ly > 0)) {
+    if (I.N < 1 || I.N > kMaxN || I.K < 1 || !I.xg || !I.yg || !std::isfinite(I.Lx) || !std::isfinite(I.Ly)) {
       g_init_error = "esdg_swe_init: instance " + std::to_string(i) + ": bad N, K, pointers or periods";
       return ESDG_EINVAL;
     }
@@ -426,10 +426,12 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
       for (size_t j = 0; j < push.size(); ++j) {
         const int32_t m = H.mapP[j], k2 = m / Nh;
         push[j] = k2 * Nfq + (m - k2 * Nh - Nq);
+        if (H.wall[j]) push[j] = int32_t(uint32_t(push[j]) | kPushWall);   // own slot, mirrored
       }
       // inverse-permutation check: every slot is filled exactly once
       std::vector<char> hit(push.size(), 0);
-      for (int32_t p : push) {
+      for (int32_t p0 : push) {
+        const int32_t p = int32_t(uint32_t(p0) & ~kPushWall);
         if (p < 0 || size_t(p) >= push.size() || hit[p]) return s->fail(ESDG_EMESH, "face push map is not a permutation");
         hit[p] = 1;
       }

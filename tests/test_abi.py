@@ -109,3 +109,20 @@ def test_init_weight_adjusted_mass():
     arr[0] = binding.esdg_swe_instance(w.N, w.K, binding._dptr(xg), binding._dptr(yg), binding._dptr(b), w.Lx, w.Ly)
     h, nb = C.c_void_p(), C.c_size_t()
     assert lib.esdg_swe_init(1, arr, C.byref(opt), C.byref(h), C.byref(nb)) == binding.ESDG_EINVAL
+
+
+def test_init_walls():
+    """A closed basin (periods 0) plans with its boundary faces as reflective walls; the same
+    mesh declared fully periodic is rejected (its boundary faces have no partner)."""
+    lib = binding.load_library()
+    w = wl.basin(n=3, N=3)
+    for L, expect in ((0.0, binding.ESDG_OK), (2.0, binding.ESDG_EMESH)):
+        xg, yg, b = (np.ascontiguousarray(a) for a in (w.xg, w.yg, w.b_nodes))
+        arr = (binding.esdg_swe_instance * 1)()
+        arr[0] = binding.esdg_swe_instance(w.N, w.K, binding._dptr(xg), binding._dptr(yg), binding._dptr(b), L, L)
+        opt = binding.make_options("fp32", "lf", 1.0, True, 0)
+        h, nb = C.c_void_p(), C.c_size_t()
+        st = lib.esdg_swe_init(1, arr, C.byref(opt), C.byref(h), C.byref(nb))
+        assert st == expect, lib.esdg_swe_last_error(None).decode()
+        if st == binding.ESDG_OK:
+            lib.esdg_swe_destroy(h)
