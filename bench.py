@@ -136,6 +136,72 @@ def cpu_baseline(w, stages_budget=75, mass="stored"):
                       f"workload, dense FP64 numpy oracle, BLAS limited to 1 thread, {t:.1f} s"}
 
 
+# FLOPs per matrix entry and element in the Section 5.4 volume terms: traditional, 2 matrices x
+# 3 fields multiply-adds (12); entropy-stable, the same plus the two-point flux (six averages
+# 12, pressure 4, flux products 6): 34
+VOLUME_FLOPS = {"traditional": 12, "entropy_stable": 34}
+
+
+def volume_ratio(args, torch):
+    """Section 5.4: time of the entropy-stable volume term over the traditional one for random
+    n x n matrices, on the GPU (HIP events, median of 5 launches, FP64 and FP32) and on one
+    host core (the oracle's plain C versions, FP64), for n = 10..250."""
+    from paper_2005_02516_amd.binding import esdg_volume_kernel
+    sizes = [int(x) for x in args.volume_sizes.split(",")]
+    rows = []
+    for n in sizes:
+        K = max(64, min(1 << 22, (1 << 28) // (n * n)))
+        rng = np.random.default_rng(n)
+        Qx, Qy = rng.standard_normal((n, n)), rng.standard_normal((n, n))
+        h = rng.uniform(1.0, 2.0, (K, n))
+        u = np.stack([h, h * rng.uniform(-0.5, 0.5, (K, n)), h * rng.uniform(-0.5, 0.5, (K, n))])
+        row = {"n": n, "K_gpu": K}
+        for prec, tdt in (("fp64", torch.float64), ("fp32", torch.float32)):
+            QxT = torch.tensor(np.ascontiguousarray(Qx.T), dtype=tdt, device="cuda:0")
+            QyT = torch.tensor(np.ascontiguousarray(Qy.T), dtype=tdt, device="cuda:0")
+            ud = torch.tensor(u, dtype=tdt, device="cuda:0")
+            r = torch.empty_like(ud)
+            t = {}
+            for kind in ("traditional", "entropy_stable"):
+                esdg_volume_kernel(kind, QxT, QyT, ud, r, 9.81)
+                times = []
+                for _ in range(5):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    esdg_volume_kernel(kind, QxT, QyT, ud, r, 9.81)
+                    e1.record()
+                    e1.synchronize()
+                    times.append(e0.elapsed_time(e1) * 1e3)
+                t[kind] = float(np.median(times))
+            row[prec] = {"t_traditional_us": round(t["traditional"], 2), "t_entropy_stable_us": round(t["entropy_stable"], 2),
+                         "R_GPU": round(t["entropy_stable"] / t["traditional"], 3),
+                         "TFLOPs_traditional": round(VOLUME_FLOPS["traditional"] * K * n * n / t["traditional"] / 1e6, 3),
+                         "TFLOPs_entropy_stable": round(VOLUME_FLOPS["entropy_stable"] * K * n * n / t["entropy_stable"] / 1e6, 3)}
+            del QxT, QyT, ud, r
+        if not args.no_cpu_baseline:
+            from oracle import volume_kernels as V
+            if not os.path.exists(V.C_LIBRARY):
+                V.build_c()
+            Kc = max(1, min(K, (1 << 21) // (n * n)))
+            tc = {}
+            for kind, key in (("dg", "traditional"), ("esdg", "entropy_stable")):
+                t0 = time.perf_counter()
+                V.c_volume(kind, Qx, Qy, u[:, :Kc], 9.81)
+                tc[key] = (time.perf_counter() - t0) / Kc
+            row["cpu_fp64_one_core"] = {"K": Kc, "t_traditional_us_per_element": round(tc["traditional"] * 1e6, 3),
+                                        "t_entropy_stable_us_per_element": round(tc["entropy_stable"] * 1e6, 3),
+                                        "R_CPU": round(tc["entropy_stable"] / tc["traditional"], 3)}
+        print(f"# n={n}: R_GPU fp64 {row['fp64']['R_GPU']}, fp32 {row['fp32']['R_GPU']}"
+              + (f", R_CPU {row['cpu_fp64_one_core']['R_CPU']}" if "cpu_fp64_one_core" in row else ""),
+              file=sys.stderr, flush=True)
+        rows.append(row)
+    print(json.dumps({"metric": "entropy-stable / traditional DG volume-kernel time ratio (Section 5.4)",
+                      "value": rows[[r["n"] for r in rows].index(50)]["fp64"]["R_GPU"] if 50 in sizes else None,
+                      "unit": "ratio (R_GPU, FP64, n=50)", "higher_is_better": False, "n_gpus": 1,
+                      "data": "synthetic: random matrices and states, seeded", "per_size": rows,
+                      "flops_per_entry": VOLUME_FLOPS}), flush=True)
+
+
 def ensemble(args, torch):
     """Batched ensemble: independent instances (K ~ U{2048..32768}, N ~ U{2,3,4}, seeded
     bathymetry and Gaussian perturbations) advanced together, one launch per RK stage."""
@@ -196,6 +262,9 @@ def main():
                     help="per-stage: one launch per RK stage (graph replays); fused: all stages of a step "
                          "call in one cooperative launch with neighbour-tile waits; auto (default): fused "
                          "when every workgroup holds one tile, which then stays in LDS")
+    ap.add_argument("--volume-ratio", action="store_true",
+                    help="the Section 5.4 volume-kernel cost ratio (entropy-stable / traditional) instead")
+    ap.add_argument("--volume-sizes", default="10,25,50,100,150,200,250")
     ap.add_argument("--walls", action="store_true",
                     help="the closed curved-wall basin (reflective walls) instead of the periodic workload")
     ap.add_argument("--mass", choices=["stored", "wadg"], default="stored",
@@ -228,6 +297,8 @@ def main():
 
     if args.ensemble:
         return ensemble(args, torch)
+    if args.volume_ratio:
+        return volume_ratio(args, torch)
     w = wl.basin(n=args.n, N=args.N) if args.walls else wl.config2(n=args.n, N=args.N)
     Np, Nq, Nfq, Nh = dims(w.N)
     dof = w.K * Np

@@ -25,6 +25,7 @@ EXPORTED = [
     "esdg_swe_init", "esdg_swe_bind", "esdg_swe_set_state", "esdg_swe_set_state_modal", "esdg_swe_get_state",
     "esdg_swe_state_device", "esdg_swe_rhs", "esdg_swe_step", "esdg_swe_diagnostics", "esdg_swe_sync",
     "esdg_swe_query", "esdg_swe_launch_info", "esdg_swe_reference_level", "esdg_swe_last_error", "esdg_swe_destroy",
+    "esdg_volume_kernel",
 ]
 
 
@@ -97,6 +98,7 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
     lib.esdg_swe_last_error.restype = C.c_char_p
     lib.esdg_swe_destroy.argtypes = [vp]
     lib.esdg_swe_destroy.restype = None
+    lib.esdg_volume_kernel.argtypes = [i32, i32, vp, vp, vp, vp, i32, i32, C.c_double, vp]
     for name in EXPORTED:
         if name not in ("esdg_swe_last_error", "esdg_swe_destroy"):
             getattr(lib, name).restype = C.c_int32
@@ -244,3 +246,28 @@ class EsdgSwe:
             self.close()
         except Exception:
             pass
+
+
+VOLUME_KINDS = {"traditional": 0, "entropy_stable": 1}
+
+
+def esdg_volume_kernel(kind: str, QxT, QyT, u, r, g: float, stream=None) -> None:
+    """The Section 5.4 volume term on the GPU (esdg_volume_kernel): torch tensors on the
+    device, QxT/QyT [n][n] (transposed matrices), u and r [3][K][n], all float64 or all
+    float32; asynchronous on ``stream`` (torch's current stream if None)."""
+    import torch
+    lib = load_library()
+    ts = (QxT, QyT, u, r)
+    if not all(t.is_cuda and t.is_contiguous() and t.dtype == u.dtype for t in ts):
+        raise ValueError("QxT, QyT, u, r must be contiguous device tensors of one dtype")
+    if u.dtype not in (torch.float64, torch.float32):
+        raise ValueError("float64 or float32 only")
+    n, K = int(u.shape[2]), int(u.shape[1])
+    if tuple(QxT.shape) != (n, n) or tuple(QyT.shape) != (n, n) or tuple(r.shape) != tuple(u.shape) or u.shape[0] != 3:
+        raise ValueError("shapes: QxT, QyT [n][n]; u, r [3][K][n]")
+    st = stream if stream is not None else torch.cuda.current_stream(u.device)
+    status = lib.esdg_volume_kernel(VOLUME_KINDS[kind], 0 if u.dtype == torch.float64 else 1,
+                                    C.c_void_p(QxT.data_ptr()), C.c_void_p(QyT.data_ptr()), C.c_void_p(u.data_ptr()),
+                                    C.c_void_p(r.data_ptr()), n, K, float(g), C.c_void_p(st.cuda_stream))
+    if status != ESDG_OK:
+        raise EsdgError(status, f"esdg_volume_kernel returned {status}")

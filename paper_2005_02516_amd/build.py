@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIBDIR = os.path.join(HERE, "_lib")
 LIBNAME = "libesdg_swe.so"
-SOURCES = ["host_setup.cpp", "kernels.hip", "runtime.cpp"]
+SOURCES = ["host_setup.cpp", "kernels.hip", "runtime.cpp", "volume_bench.hip"]
 
 HIPFLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

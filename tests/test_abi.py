@@ -14,8 +14,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_symbols():
-    text = open(os.path.join(ROOT, "include", "esdg_swe.h")).read()
-    return sorted(set(re.findall(r"\b(esdg_swe_[a-z_]+)\s*\(", text)))
+    """Every function the headers under include/ declare (esdg_swe_* and esdg_volume_*)."""
+    names = set()
+    for f in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if f.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", f)).read()
+            names |= set(re.findall(r"\b(esdg_(?:swe|volume)_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_symbols_exported():
