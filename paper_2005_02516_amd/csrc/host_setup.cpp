@@ -1,5 +1,5 @@
-// Host-side FP64 setup: reference element, isoparametric geometry, periodic connectivity
-// and inverse curved mass matrices.  See host_setup.hpp.
+// Host-side FP64 setup: reference element, isoparametric geometry, face connectivity
+// (periodic, or reflective walls) and inverse curved mass matrices.  See host_setup.hpp.
 #include "host_setup.hpp"
 
 #include <algorithm>

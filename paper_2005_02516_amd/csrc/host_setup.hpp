@@ -1,7 +1,8 @@
 // Host-side FP64 setup for the ESDG shallow-water library: reference element of degree
 // N (basis, quadrature, hybridized SBP operators) and per-instance mesh data (isoparametric
-// geometry, periodic connectivity, inverse curved mass matrices).  Nothing here is timed:
-// it runs once in esdg_swe_init, before any device work.
+// geometry, face connectivity with periodic partners or reflective walls, inverse curved
+// mass matrices or the weights of their weight-adjusted form).  Nothing here is timed: it
+// runs once in esdg_swe_init, before any device work.
 #pragma once
 
 #include <cstdint>

@@ -1,10 +1,10 @@
-// HIP kernels (gfx950) for one RK stage of the modal ESDG shallow-water scheme.
+// HIP kernels (gfx950) for the RK stages of the modal ESDG shallow-water scheme.
 //
 // One workgroup processes a tile of consecutive elements of one instance:
-//   0. every global array the tile needs (entropy-projected values of the tile and of
-//      its face neighbours, metric factors, state, RK register, inverse mass matrices,
-//      weights, bathymetry) is fetched into LDS in one phase, so the global-memory
-//      latency is exposed once per tile;
+//   0. every global array the tile needs (its entropy-projected values, the values its
+//      face neighbours pushed into its slots, metric factors, state, RK register, the
+//      static block of mass data, weights, bathymetry and push targets) is fetched into
+//      LDS with asynchronous copies, so the global-memory latency is exposed once per tile;
 //   1. node records at the Nh hybridized nodes are built in LDS;
 //   2. flux differencing in skew form (Section 5.2, Step 4): every row m of every
 //      nonzero block of Q_skew = Q_h - Q_h^T (volume-volume and volume-surface; the zero
@@ -15,10 +15,15 @@
 //      1/2 g h_m (H_n - Href) Q_mn (exact because Q_h 1 = 0);
 //   3. interface flux f_S(u~+, u~), boundary half of the source and optional local
 //      Lax-Friedrichs penalty (Section 2.8) on the face rows;
-//   4. lift rhs = -(M_h^k)^{-1} V_h^T r_h with the stored inverses (Section 2.8);
+//   4. lift rhs = -(M_h^k)^{-1} V_h^T r_h, with the stored inverses (Section 2.8) or the
+//      weight-adjusted inverse named after eq. (dgform);
 //   5. LSRK update (Section 4), then, fused, the entropy projection of the updated state
-//      (Section 2.6) written to the other stage buffer for the next stage.
-// The launch boundary is the grid-wide barrier the neighbour gather needs.
+//      (Section 2.6), written to the other stage buffer and pushed into the face slots of
+//      the neighbours (or, on a reflective wall, Section 2.9, the mirror state into the
+//      node's own slot).
+// Between stages the face exchange needs every neighbour's projection: either the launch
+// boundary (one launch per stage) or, in a multi-stage launch, per-tile progress counts
+// that a tile waits on before it reads its neighbours' values.
 //
 // Depth is carried as the free-surface anomaly eta = h + b - Href (Href a per-instance
 // constant), so the projection works on v1 - g Href and no quantity of size g H is

@@ -167,3 +167,50 @@ def test_basin_bench_size_rows(torch):
     ok, worst = check_rhs(r, o.rhs(uh), rhs_abs_bound(o, uh, ks), EPS32)
     print(f"basin 8192 fp32: worst err / (eps * bound) = {worst:.3f}", flush=True)
     assert ok, worst
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_walls_with_weight_adjusted_inverse(torch, precision):
+    """Walls and the weight-adjusted mass inverse together: one RHS against the oracle with
+    both, and the multi-stage launch bitwise equal to per-stage launches."""
+    from paper_2005_02516_amd.binding import EsdgSwe
+    w = moving_basin(3, 3)
+    s = EsdgSwe([w], precision=precision, flux="lf", g=w.g, mass="wadg")
+    s.set_state(0, w.u_nodes)
+    uh = s.get_state(0)
+    r = rhs_of(torch, s)
+    s.close()
+    d = O.Discretization(w.N, w.xg, w.yg, w.b_nodes, w.g, w.Lx, w.Ly, mass="wadg")
+    o = O.Oracle(d, "lf", Href=O.mean_free_surface(d, uh))
+    ok, worst = check_rhs(r, o.rhs(uh), rhs_abs_bound(o, uh, np.arange(w.K)), EPS64 if precision == "fp64" else EPS32)
+    assert ok, worst
+    out = []
+    for fused in (False, True):
+        s = EsdgSwe([w], precision=precision, flux="lf", g=w.g, mass="wadg", fused=fused)
+        s.set_state(0, w.u_nodes)
+        s.step(w.dt, 5)
+        out.append(s.get_state(0))
+        s.close()
+    assert np.array_equal(out[0], out[1])
+
+
+def test_walls_in_mixed_ensemble(torch):
+    """A walled basin next to periodic instances of other degrees in one handle: each
+    instance's 3 FP64 steps match its own oracle."""
+    from paper_2005_02516_amd.binding import EsdgSwe
+    ws = [moving_basin(3, 2), wl.config2(n=3, N=3), moving_basin(2, 4)]
+    s = EsdgSwe(ws, precision="fp64", flux="lf", g=1.0)
+    uh0 = []
+    for i, w in enumerate(ws):
+        s.set_state(i, w.u_nodes)
+        uh0.append(s.get_state(i))
+    dt = min(w.dt for w in ws)
+    s.step(np.full(len(ws), dt), 3)
+    got = [s.get_state(i) for i in range(len(ws))]
+    s.close()
+    for w, u0, u in zip(ws, uh0, got):
+        d, o = oracle_for(w, "lf")
+        ur, _ = O.run(o, u0, dt, 3)
+        hn = np.linalg.norm(ur[0])
+        err = max(np.linalg.norm(u[c] - ur[c]) / hn for c in range(3))
+        assert err < 1e-12, (w.name, w.N, err)
