@@ -449,7 +449,7 @@ __device__ __forceinline__ int stat_head(int nstat) {
 }
 
 // Phase 0: fetch the tile's global data into LDS (all asynchronous; see above).
-template <typename real, int N, bool WADG>
+template <typename real, int N, bool WADG, bool MULTI>
 __device__ __forceinline__ void fetch_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, Lds<real, N> &L) {
   constexpr int Np = dim_Np(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
   constexpr int W = sizeof(real) / 4;     // 32-bit words per value
@@ -485,7 +485,7 @@ __device__ __forceinline__ void fetch_tile(const StageArgs &a, const InstDesc &d
   }
   if (a.mode != kProject) {        // neighbour values, pushed here by the neighbours' projections
     const uint32_t *src = words(static_cast<const real *>(d.nbx[a.in_buf]) + size_t(k0) * Nfq * 4);
-    if (a.progress)                // multi-stage launch: written during this kernel, maybe on another XCD
+    if (MULTI && a.progress)       // multi-stage launch: written during this kernel, maybe on another XCD
       async_copy_words<kCpolAgent>(lwords(L.nb), src, ne * Nfq * 4 * W);
     else
       async_copy_words(lwords(L.nb), src, ne * Nfq * 4 * W);
@@ -682,7 +682,7 @@ __device__ __forceinline__ void interface_tile(const InstDesc &d, int ne, Lds<re
   }
 }
 
-template <typename real, int N, int R, int CM, bool WADG>
+template <typename real, int N, int R, int CM, bool WADG, bool MULTI>
 __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm, real *tile,
                                            int res = 0, int t = 0, int target = 0) {
   constexpr int Np = dim_Np(N), Nh = dim_Nh(N), Nfq = dim_Nfq(N);
@@ -694,7 +694,7 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
   const bool keep = (res & kResident) && !(res & kResLast);   // state stays in LDS only
   // a resident tile after its first stage has everything but the neighbour values in LDS;
   // it fetches those after the pair loop, once its neighbours have pushed them
-  if (!mid) fetch_tile<real, N, WADG>(a, d, k0, ne, L);
+  if (!mid) fetch_tile<real, N, WADG, MULTI>(a, d, k0, ne, L);
   // head of the static block: loaded into registers now, while the node records and the
   // residual run, and written to LDS before the barrier that ends the residual
   constexpr int W = sizeof(real) / 4;
@@ -712,7 +712,7 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
   if (a.mode == kProject) {
     __syncthreads();
     project_tile<real, N, CM, WADG>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]),
-                              static_cast<real *>(d.nbx[a.out_buf]), a.flag, a.progress != nullptr);
+                              static_cast<real *>(d.nbx[a.out_buf]), a.flag, MULTI && a.progress != nullptr);
     return true;
   }
   __syncthreads();
@@ -815,7 +815,7 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
   if (a.mode == kStage) {
     __syncthreads();
     project_tile<real, N, CM, WADG>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]),
-                              static_cast<real *>(d.nbx[a.out_buf]), a.flag, a.progress != nullptr, res);
+                              static_cast<real *>(d.nbx[a.out_buf]), a.flag, MULTI && a.progress != nullptr, res);
   }
   return true;
 }
@@ -831,7 +831,7 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
 // tiles have finished the previous one (see wait_neighbours), which the co-residency of
 // all workgroups (cooperative launch) makes safe.  A wait that gives up sets flag bit 1
 // and ends the workgroup; its neighbours' waits then give up in turn.
-template <typename real, int CM, bool WADG>
+template <typename real, int CM, bool WADG, bool MULTI>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel(StageArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -841,7 +841,9 @@ stage_kernel(StageArgs a) {
   const int chunk = (int(blockIdx.x) % kXcds) * (G / kXcds) + int(blockIdx.x) / kXcds;
   const int t0 = a.ranges ? read_const(a.ranges, chunk) : int((long long)chunk * a.ntiles / G);
   const int t1 = a.ranges ? read_const(a.ranges, chunk + 1) : int((long long)(chunk + 1) * a.ntiles / G);
-  const bool multi = a.progress != nullptr;
+  // MULTI: the multi-stage instantiation; the per-stage one compiles without the waits,
+  // resident tiles and device-coherent pushes (and keeps the registers they would cost)
+  const bool multi = MULTI && a.progress != nullptr;
   // resident: the launch gives this workgroup at most one tile (cost-balanced ranges can
   // still give a workgroup two; that one then re-reads its tiles every stage)
   const bool resident = multi && a.resident && t1 - t0 <= 1;
@@ -875,11 +877,11 @@ stage_kernel(StageArgs a) {
       }
       bool ok = true;
       switch (d.N) {
-        case 1: ok = stage_tile<real, 1, RowsPerThread<real, 1>::value, CM, WADG>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
-        case 2: ok = stage_tile<real, 2, RowsPerThread<real, 2>::value, CM, WADG>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
-        case 3: ok = stage_tile<real, 3, RowsPerThread<real, 3>::value, CM, WADG>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
-        case 4: ok = stage_tile<real, 4, RowsPerThread<real, 4>::value, CM, WADG>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
-        case 5: ok = stage_tile<real, 5, RowsPerThread<real, 5>::value, CM, WADG>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
+        case 1: ok = stage_tile<real, 1, RowsPerThread<real, 1>::value, CM, WADG, MULTI>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
+        case 2: ok = stage_tile<real, 2, RowsPerThread<real, 2>::value, CM, WADG, MULTI>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
+        case 3: ok = stage_tile<real, 3, RowsPerThread<real, 3>::value, CM, WADG, MULTI>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
+        case 4: ok = stage_tile<real, 4, RowsPerThread<real, 4>::value, CM, WADG, MULTI>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
+        case 5: ok = stage_tile<real, 5, RowsPerThread<real, 5>::value, CM, WADG, MULTI>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
         default: break;
       }
       if (!ok) {
@@ -955,18 +957,27 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagArgs a) {
 
 // ---------------------------------------------------------------- host launchers
 
-template <bool WADG>
-static const void *stage_fn_mass(bool fp64, int cm) {
+template <bool WADG, bool MULTI>
+static const void *stage_fn_mode(bool fp64, int cm) {
   if (fp64)
-    return cm == kMfmaNative ? reinterpret_cast<const void *>(&stage_kernel<double, kMfmaNative, WADG>)
-                             : reinterpret_cast<const void *>(&stage_kernel<double, kValu, WADG>);
-  if (cm == kMfmaBf16x3) return reinterpret_cast<const void *>(&stage_kernel<float, kMfmaBf16x3, WADG>);
-  if (cm == kMfmaNative) return reinterpret_cast<const void *>(&stage_kernel<float, kMfmaNative, WADG>);
-  return reinterpret_cast<const void *>(&stage_kernel<float, kValu, WADG>);
+    return cm == kMfmaNative ? reinterpret_cast<const void *>(&stage_kernel<double, kMfmaNative, WADG, MULTI>)
+                             : reinterpret_cast<const void *>(&stage_kernel<double, kValu, WADG, MULTI>);
+  if (cm == kMfmaBf16x3) return reinterpret_cast<const void *>(&stage_kernel<float, kMfmaBf16x3, WADG, MULTI>);
+  if (cm == kMfmaNative) return reinterpret_cast<const void *>(&stage_kernel<float, kMfmaNative, WADG, MULTI>);
+  return reinterpret_cast<const void *>(&stage_kernel<float, kValu, WADG, MULTI>);
 }
 
-static const void *stage_fn(bool fp64, int cm, bool wadg) {
-  return wadg ? stage_fn_mass<true>(fp64, cm) : stage_fn_mass<false>(fp64, cm);
+// The stage kernel for a precision, contraction mode, mass inverse and launch kind (one
+// launch per stage, or all stages of a step call in one cooperative launch).  One launch
+// per stage uses the leaner per-stage instantiation, except for the FP32 vector-ALU kernel:
+// there the multi-stage instantiation (which runs as a per-stage kernel when given no
+// progress counts) was measured faster on balance (same box: N=4 1.4 %, N=5 5 %, the
+// mixed-degree ensemble 11 %; the per-stage build is faster only at N=3, by 8 %), while
+// the per-stage build is 7-11 % faster in FP64 and 6 % with split-bf16 contractions.
+static const void *stage_fn(bool fp64, int cm, bool wadg, bool multi) {
+  if (!fp64 && cm == kValu) multi = true;
+  if (wadg) return multi ? stage_fn_mode<true, true>(fp64, cm) : stage_fn_mode<true, false>(fp64, cm);
+  return multi ? stage_fn_mode<false, true>(fp64, cm) : stage_fn_mode<false, false>(fp64, cm);
 }
 
 // Workgroups of the stage kernel that stay resident on the whole device.
@@ -976,8 +987,13 @@ hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, size_t lds_bytes, int 
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stage_fn(fp64, cm, wadg), kBlock, lds_bytes);
-  if (e != hipSuccess) return e;
+  // both launch kinds use the same grid: the smaller residency of the two kernels
+  for (int multi = 0; multi < 2; ++multi) {
+    int n = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stage_fn(fp64, cm, wadg, multi != 0), kBlock, lds_bytes);
+    if (e != hipSuccess) return e;
+    per_cu = multi ? std::min(per_cu, n) : n;
+  }
   // The occupancy query does not round the LDS request up to the allocation granule; a
   // workgroup count it reports can then fail to fit, and the persistent grid's surplus
   // blocks only start when others finish.  Cap it with 1 KiB granules of the CU's LDS.
@@ -991,7 +1007,10 @@ hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, size_t lds_bytes, int 
 }
 
 hipError_t set_stage_lds_limit(bool fp64, int cm, bool wadg, size_t lds_bytes) {
-  return hipFuncSetAttribute(stage_fn(fp64, cm, wadg), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
+  hipError_t e = hipFuncSetAttribute(stage_fn(fp64, cm, wadg, false), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    int(lds_bytes));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(stage_fn(fp64, cm, wadg, true), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
 }
 
 // Persistent grid: at most max_blocks (what stays resident), at most one block per tile,
@@ -1007,8 +1026,8 @@ hipError_t launch_stage(bool fp64, const StageArgs &a, int max_blocks, size_t ld
   const int grid = stage_grid(a.ntiles, max_blocks);
   StageArgs arg = a;
   void *params[] = {&arg};
-  return hipLaunchKernel(stage_fn(fp64, a.contraction, a.wadg != 0), dim3(grid), dim3(kBlock), params, lds_bytes,
-                         stream);
+  return hipLaunchKernel(stage_fn(fp64, a.contraction, a.wadg != 0, false), dim3(grid), dim3(kBlock), params,
+                         lds_bytes, stream);
 }
 
 // Multi-stage launch: every workgroup of the grid must be resident at once (tiles wait on
@@ -1018,7 +1037,7 @@ hipError_t launch_stage_fused(bool fp64, const StageArgs &a, int max_blocks, siz
   const int grid = stage_grid(a.ntiles, max_blocks);
   StageArgs arg = a;
   void *params[] = {&arg};
-  return hipLaunchCooperativeKernel(stage_fn(fp64, a.contraction, a.wadg != 0), dim3(grid), dim3(kBlock), params,
+  return hipLaunchCooperativeKernel(stage_fn(fp64, a.contraction, a.wadg != 0, true), dim3(grid), dim3(kBlock), params,
                                     lds_bytes, stream);
 }
 
