@@ -68,15 +68,18 @@ STEP_MODES = {0: "one launch per RK stage (HIP graph replays)",
 
 
 def kernel_source_hash():
-    """sha256 of the stage kernel's code (kernels.hip + device_types.hpp) with // comments,
-    trailing blanks and empty lines removed, so that editing a comment does not void a
-    counter summary taken on the same code."""
+    """sha256 of the stage kernel's device code: kernels.hip up to its host launchers, and
+    device_types.hpp, with // comments, trailing blanks and empty lines removed, so that a
+    comment or a host-side change does not void a counter summary taken on the same kernel
+    (which kernel build a launch plan uses is part of the plan a summary records)."""
     import hashlib
     import re
     h = hashlib.sha256()
     for f in ("kernels.hip", "device_types.hpp"):
         with open(os.path.join(ROOT, "paper_2005_02516_amd", "csrc", f)) as fh:
             for line in fh:
+                if f == "kernels.hip" and "-- host launchers" in line:
+                    break
                 code = re.sub(r"//.*$", "", line).rstrip()
                 if code:
                     h.update(code.encode() + b"\n")

@@ -53,8 +53,9 @@ def tile_words(N: int, E: int) -> int:
 
 
 # LDS per workgroup at which four workgroups share a CU (160 KiB), the residency the stage
-# kernel's register budget allows
+# kernel's register budget allows, and the static LDS the kernel adds to the dynamic request
 LDS_FOUR_PER_CU = 40 * 1024
+STATIC_LDS = 256
 
 
 def fit_mixed(precision: str, epb: Dict[int, int]) -> Dict[int, int]:
@@ -66,11 +67,11 @@ def fit_mixed(precision: str, epb: Dict[int, int]) -> Dict[int, int]:
         return dict(epb)
     word = 8 if precision == "fp64" else 4
     ref_max = max(ref_words(N) for N in epb)
-    alone = max((ref_words(N) + tile_words(N, E)) * word for N, E in epb.items())
+    alone = max((ref_words(N) + tile_words(N, E)) * word + STATIC_LDS for N, E in epb.items())
     budget = max(LDS_FOUR_PER_CU, alone)
     out = {}
     for N, E in epb.items():
-        while E > 1 and (ref_max + tile_words(N, E)) * word > budget:
+        while E > 1 and (ref_max + tile_words(N, E)) * word + STATIC_LDS > budget:
             E = max(c for c in CANDIDATES if c < E)
         out[N] = E
     return out
@@ -122,7 +123,8 @@ def lds_ok(N: int, E: int, precision: str) -> bool:
     return (ref_words(N) + tile_words(N, E)) * word <= 160 * 1024 and E * Nh <= 2048
 
 
-def tune(cases: List[Tuple[int, int]], precisions=("fp32", "fp64"), write: bool = True, log=sys.stderr):
+def tune(cases: List[Tuple[int, int]], precisions=("fp32", "fp64"), write: bool = True, log=sys.stderr,
+         out: Optional[str] = None):
     from . import workloads as wl
     data = _load()
     entries = data.setdefault("entries", {})
@@ -141,7 +143,7 @@ def tune(cases: List[Tuple[int, int]], precisions=("fp32", "fp64"), write: bool 
     data["device"] = "gfx950 (MI355X)"
     data["note"] = "written by `python -m paper_2005_02516_amd.autotune --write` on the GPU"
     if write:
-        with open(CACHE, "w") as f:
+        with open(out or CACHE, "w") as f:
             json.dump(data, f, indent=1, sort_keys=True)
     return data
 
@@ -152,5 +154,7 @@ DEFAULT_CASES = [(1, 64), (2, 64), (3, 64), (4, 64), (5, 64), (2, 256), (3, 256)
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--write", action="store_true")
+    ap.add_argument("--precisions", default="fp32,fp64", help="comma-separated: fp32, fp64")
+    ap.add_argument("--out", default=None, help="write the cache here instead of the package's file")
     args = ap.parse_args()
-    tune(DEFAULT_CASES, write=args.write)
+    tune(DEFAULT_CASES, precisions=tuple(args.precisions.split(",")), write=args.write, out=args.out)

@@ -987,21 +987,29 @@ hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, size_t lds_bytes, int 
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  // both launch kinds use the same grid: the smaller residency of the two kernels
-  for (int multi = 0; multi < 2; ++multi) {
-    int n = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stage_fn(fp64, cm, wadg, multi != 0), kBlock, lds_bytes);
-    if (e != hipSuccess) return e;
-    per_cu = multi ? std::min(per_cu, n) : n;
-  }
   // The occupancy query does not round the LDS request up to the allocation granule; a
   // workgroup count it reports can then fail to fit, and the persistent grid's surplus
-  // blocks only start when others finish.  Cap it with 1 KiB granules of the CU's LDS.
+  // blocks only start when others finish (for a multi-stage launch, which needs every
+  // workgroup resident at once, their neighbours then wait for stages that cannot come).
+  // So cap it with 1 KiB granules of the CU's LDS, counting the kernel's own static LDS
+  // (the multi-stage build's workgroup reduction) on top of the dynamic request.  Both
+  // launch kinds use the same grid: the smaller residency of the two builds.
   int lds_cu = 0;
   e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
   if (e != hipSuccess) return e;
-  const size_t granule = 1024, need = (lds_bytes + granule - 1) / granule * granule;
-  if (need > 0 && lds_cu > 0) per_cu = std::min<long long>(per_cu, (long long)(size_t(lds_cu) / need));
+  for (int multi = 0; multi < 2; ++multi) {
+    const void *fn = stage_fn(fp64, cm, wadg, multi != 0);
+    int n = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kBlock, lds_bytes);
+    if (e != hipSuccess) return e;
+    hipFuncAttributes fa{};
+    e = hipFuncGetAttributes(&fa, fn);
+    if (e != hipSuccess) return e;
+    const size_t granule = 1024, total = lds_bytes + fa.sharedSizeBytes;
+    const size_t need = (total + granule - 1) / granule * granule;
+    if (need > 0 && lds_cu > 0) n = std::min<long long>(n, (long long)(size_t(lds_cu) / need));
+    per_cu = multi ? std::min(per_cu, n) : n;
+  }
   *out = ncu * (per_cu > 0 ? per_cu : 1);
   return hipSuccess;
 }

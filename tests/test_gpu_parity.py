@@ -374,3 +374,21 @@ def test_fused_steps_mixed_ensemble(torch):
     got = _run_steps(ws, "fp32", 4, fused=True)
     for a, b in zip(ref, got):
         assert np.array_equal(a, b)
+
+
+def test_fused_residency_counts_static_lds(torch):
+    """FP64, N=2, 12 elements per tile on 8192 elements (683 tiles): 54240 bytes of dynamic
+    LDS plus the multi-stage build's own 256 bytes fit twice per CU in 1 KiB granules of
+    160 KiB, not three times, so the automatic plan must not make it a resident
+    multi-stage launch; a forced multi-stage launch (two tiles per workgroup on the grid
+    that is really resident) matches per-stage launches bitwise."""
+    w = wl.config2(n=64, N=2)
+    s = solver(w, "fp64", "lf", elems_per_block=12)
+    info = s.launch_info()
+    s.close()
+    assert info["tiles"] == 683 and info["step_mode"] == 0, info
+    assert info["resident_workgroups"] < info["tiles"], info
+    ref = _run_steps([w], "fp64", 3, fused=False, elems_per_block=12)
+    auto = _run_steps([w], "fp64", 3, elems_per_block=12)
+    forced = _run_steps([w], "fp64", 3, fused=True, elems_per_block=12)
+    assert np.array_equal(ref[0], auto[0]) and np.array_equal(ref[0], forced[0])
