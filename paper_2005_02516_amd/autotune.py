@@ -19,7 +19,7 @@ from typing import Dict, Iterable, List, Optional, Tuple
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tune_cache_gfx950.json")
-CANDIDATES = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32)
+CANDIDATES = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64)
 
 
 def size_class(K: int) -> str:
@@ -148,7 +148,7 @@ def tune(cases: List[Tuple[int, int]], precisions=("fp32", "fp64"), write: bool 
     return data
 
 
-DEFAULT_CASES = [(1, 64), (2, 64), (3, 64), (4, 64), (5, 64), (2, 256), (3, 256), (4, 256), (5, 256)]
+DEFAULT_CASES = [(1, 64), (2, 64), (3, 64), (4, 64), (5, 64), (1, 256), (2, 256), (3, 256), (4, 256), (5, 256)]
 
 
 if __name__ == "__main__":
@@ -156,5 +156,8 @@ if __name__ == "__main__":
     ap.add_argument("--write", action="store_true")
     ap.add_argument("--precisions", default="fp32,fp64", help="comma-separated: fp32, fp64")
     ap.add_argument("--out", default=None, help="write the cache here instead of the package's file")
+    ap.add_argument("--cases", default=None,
+                    help="comma-separated N:n (degree, squares per side of the config-2 mesh); default: all")
     args = ap.parse_args()
-    tune(DEFAULT_CASES, precisions=tuple(args.precisions.split(",")), write=args.write, out=args.out)
+    cases = DEFAULT_CASES if not args.cases else [tuple(int(v) for v in c.split(":")) for c in args.cases.split(",")]
+    tune(cases, precisions=tuple(args.precisions.split(",")), write=args.write, out=args.out)
