@@ -222,6 +222,27 @@ def test_ragged_tiles_and_small_meshes(torch):
         assert np.all(err < 1e-11), (n, N, epb, err)
 
 
+def test_large_tiles(torch):
+    """Tile sizes up to the ABI's 64 elements (the tuned sizes for large N=1 meshes), with
+    ragged last tiles: one FP64 RHS against the oracle, and 3 FP32 steps of the multi-stage
+    launch bitwise equal to per-stage launches."""
+    for n, N, epb in ((8, 1, 32), (7, 1, 48), (9, 1, 64), (6, 2, 32)):
+        w = wl.config2(n=n, N=N)
+        d, o = oracle_for(w, "lf")
+        s = solver(w, "fp64", "lf", elems_per_block=epb)
+        s.set_state(0, w.u_nodes)
+        st = s.state_device(0)
+        rhs = torch.empty_like(st)
+        s.rhs(0, st, rhs)
+        s.sync()
+        err = rel_field_err(rhs.cpu().numpy(), o.rhs(s.get_state(0)), scale=1.0)
+        s.close()
+        assert np.all(err < 1e-11), (n, N, epb, err)
+        ref = _run_steps([w], "fp32", 3, fused=False, elems_per_block=epb)
+        got = _run_steps([w], "fp32", 3, fused=True, elems_per_block=epb)
+        assert all(np.array_equal(a, b) for a, b in zip(ref, got)), (n, N, epb)
+
+
 def test_batched_mixed_instances(torch):
     """Several instances with different N and K in one solver: each matches its own oracle."""
     ws = wl.config4_instances(count=4, n_override=[3, 4, 2, 5], N_override=[2, 3, 4, 3])
