@@ -151,6 +151,19 @@ def tune(cases: List[Tuple[int, int]], precisions=("fp32", "fp64"), write: bool 
 DEFAULT_CASES = [(1, 64), (2, 64), (3, 64), (4, 64), (5, 64), (1, 256), (2, 256), (3, 256), (4, 256), (5, 256)]
 
 
+def parse_cases(text: Optional[str]) -> List[Tuple[int, int]]:
+    """"N:n,N:n,..." (degree, squares per side of the config-2 mesh) -> cases; empty: all."""
+    if not text:
+        return list(DEFAULT_CASES)
+    cases = []
+    for item in text.split(","):
+        N, n = (int(v) for v in item.split(":"))
+        if not (1 <= N <= 5 and n >= 1):
+            raise ValueError(f"bad case {item!r}: need 1 <= N <= 5 and n >= 1")
+        cases.append((N, n))
+    return cases
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--write", action="store_true")
@@ -159,5 +172,4 @@ if __name__ == "__main__":
     ap.add_argument("--cases", default=None,
                     help="comma-separated N:n (degree, squares per side of the config-2 mesh); default: all")
     args = ap.parse_args()
-    cases = DEFAULT_CASES if not args.cases else [tuple(int(v) for v in c.split(":")) for c in args.cases.split(",")]
-    tune(cases, precisions=tuple(args.precisions.split(",")), write=args.write, out=args.out)
+    tune(parse_cases(args.cases), precisions=tuple(args.precisions.split(",")), write=args.write, out=args.out)
