@@ -14,6 +14,7 @@ Prints one JSON line.  Only one GPU is supported: --gpus > 1 exits with a messag
 from __future__ import annotations
 
 import argparse
+import glob
 import json
 import math
 import os
@@ -59,8 +60,7 @@ def alg_bytes_per_elem(N, word, wadg=False):
     return word * (12 * Np + 6 * Nfq + 2 * Np + Np + (Nq if wadg else Np * Np))
 
 
-TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
-                 ("stage_kernel_curved_N3_K8192_fp32_traffic.txt", "stage_kernel_curved_N3_K8192_fp32_fused_traffic.txt")]
+TRAFFIC_FILES = sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.txt")))
 FUSED_ARG = {"auto": "auto", "per-stage": False, "fused": True}
 STEP_MODES = {0: "one launch per RK stage (HIP graph replays)",
               1: "one cooperative launch per step call, tiles re-read every stage",
@@ -104,11 +104,28 @@ def measured_traffic(w, prec, epb, step_mode, stages_per_launch):
             continue
         if int(kv.get("stages_per_launch", -1)) != stages_per_launch:
             continue
-        if not (w.N == 3 and w.K == 8192 and prec == "fp32" and epb == 8):
+        if (int(kv.get("N", -1)), int(kv.get("K", -1)), kv.get("precision"), int(kv.get("epb", -1))) != \
+                (w.N, w.K, prec, epb):
             continue
         return {"fetch": int(kv["fetch_bytes"]), "write": int(kv["write_bytes"]),
                 "source": os.path.relpath(path, ROOT)}
     return None
+
+
+def kernel_trace_summary(w, args):
+    """The committed rocprofv3 kernel-trace summary of this workload, if there is one."""
+    name = None
+    if args.matrix_cores:
+        name = None
+    elif args.precision == "bf16x3":
+        name = "stage_kernel_bf16x3_N5_K524288.md" if (w.N, w.K) == (5, 524288) else None
+    elif args.walls:
+        name = "stage_kernel_walls_basin_N3_K8192.md" if (w.N, w.K) == (3, 8192) else None
+    elif args.mass == "wadg":
+        name = {(3, 8192): "stage_kernel_wadg_N3_K8192.md", (5, 524288): "stage_kernel_wadg_N5_K524288.md"}.get((w.N, w.K))
+    else:
+        name = {(3, 8192): "stage_kernel_curved_N3_K8192.md", (5, 524288): "stage_kernel_curved_N5_K524288.md"}.get((w.N, w.K))
+    return f"profiles/{name}" if name and os.path.exists(os.path.join(ROOT, "profiles", name)) else None
 
 
 def time_steps(s, dt, steps, torch):
@@ -369,13 +386,14 @@ def main():
                                   "counters": "FETCH_SIZE x2.0 + WRITE_SIZE x1.0 (copy-calibrated)",
                                   "source": tr["source"]}
     roof["kernel"] = "stage_kernel (fused RK stage: flux differencing + interface + lift + update + projection)"
+    trace_summary = kernel_trace_summary(w, args)
     # a multi-stage launch covers 5 * steps stages: its algorithmic work and its duration are
     # both that many stages', so the per-stage figures give the same rates
     roof["per_stage"] = {"alg_flops": flops, "alg_bytes": byts, "duration_us": round(t_stage * 1e6, 3),
                          "stages_per_launch": stages_per_launch,
-                         "duration_source": "HIP events on the solver stream over the timed steps, per RK stage "
-                                            "(rocprofv3 kernel traces of the same command: "
-                                            "profiles/stage_kernel_curved_N3_K8192.md)",
+                         "duration_source": "HIP events on the solver stream over the timed steps, per RK stage"
+                                            + (f" (rocprofv3 kernel trace of this workload: {trace_summary})"
+                                               if trace_summary else ""),
                          "other_bound": ({"hbm_GBs": round(achieved_gbs, 1), "frac": round(frac_hbm, 4)}
                                          if roof["bound"] == "alu" else
                                          {"alu_TFLOPs": round(achieved_tf, 3), "frac": round(frac_alu, 4)})}

@@ -35,7 +35,8 @@ def test_traffic_summaries_well_formed():
     found = _summaries(b)
     assert found, "no committed HBM counter summary"
     for path, kv in found:
-        for key in ("kernel_source_sha256", "step_mode", "stages_per_launch", "fetch_bytes", "write_bytes"):
+        for key in ("kernel_source_sha256", "N", "K", "precision", "epb", "step_mode", "stages_per_launch",
+                    "fetch_bytes", "write_bytes"):
             assert key in kv, (path, key)
         assert int(kv["fetch_bytes"]) > 0 and int(kv["write_bytes"]) > 0
         assert int(kv["step_mode"]) in (0, 1, 2)
@@ -44,14 +45,23 @@ def test_traffic_summaries_well_formed():
 
 def test_traffic_lookup_matches_only_its_configuration():
     b = _bench()
-    w = types.SimpleNamespace(N=3, K=8192)
     for path, kv in _summaries(b):
         if kv["kernel_source_sha256"] != b.kernel_source_hash():
             continue  # taken on an older kernel source: never reported
+        N, K, prec, epb = int(kv["N"]), int(kv["K"]), kv["precision"], int(kv["epb"])
+        w = types.SimpleNamespace(N=N, K=K)
+        other = "fp64" if prec == "fp32" else "fp32"
         mode, spl = int(kv["step_mode"]), int(kv["stages_per_launch"])
-        tr = b.measured_traffic(w, "fp32", 8, mode, spl)
-        assert tr is not None and tr["fetch"] == int(kv["fetch_bytes"])
-        assert b.measured_traffic(w, "fp32", 8, mode, spl + 5) is None
-        assert b.measured_traffic(w, "fp64", 8, mode, spl) is None
-        assert b.measured_traffic(w, "fp32", 4, mode, spl) is None
-        assert b.measured_traffic(types.SimpleNamespace(N=4, K=8192), "fp32", 8, mode, spl) is None
+        tr = b.measured_traffic(w, prec, epb, mode, spl)
+        assert tr is not None and tr["fetch"] == int(kv["fetch_bytes"]), path
+        assert b.measured_traffic(w, prec, epb, mode, spl + 5) is None
+        assert b.measured_traffic(w, other, epb, mode, spl) is None
+        assert b.measured_traffic(w, prec, epb + 1, mode, spl) is None
+        assert b.measured_traffic(types.SimpleNamespace(N=N % 5 + 1, K=K), prec, epb, mode, spl) is None
+        assert b.measured_traffic(types.SimpleNamespace(N=N, K=K + 2), prec, epb, mode, spl) is None
+
+
+def test_traffic_summaries_cover_the_benchmarked_plans():
+    """Config 2 in both launch plans and the N=5, K=524288 per-stage launch have summaries."""
+    keys = {(kv["N"], kv["K"], kv["step_mode"]) for _, kv in _summaries(_bench())}
+    assert {("3", "8192", "0"), ("3", "8192", "2"), ("5", "524288", "0")} <= keys
