@@ -270,6 +270,30 @@ def ensemble(args, torch):
     if "fp64" in res and args.precision != "fp64":
         out["fp64_value"] = dof / (res["fp64"] * 1e-3 / (5 * args.steps))
         out["speedup_vs_fp64"] = out["value"] / out["fp64_value"]
+    # roofline of the one stage kernel launch that serves every instance, on algorithmic
+    # FLOPs and bytes summed over the instances (no counter summary is taken for this mix)
+    wadg = args.mass == "wadg"
+    word = 8 if args.precision == "fp64" else 4
+    flops = sum(alg_flops_per_elem(w.N, wadg) * w.K for w in ws)
+    byts = sum(alg_bytes_per_elem(w.N, word, wadg) * w.K for w in ws)
+    tf, gbs = flops / t_stage / 1e12, byts / t_stage / 1e9
+    peak_alu = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_FP32_TFLOPS
+    if tf / peak_alu >= gbs / PEAK_HBM_GBS:
+        roof = {"bound": "alu", "achieved": round(tf, 3), "peak": peak_alu, "unit": "TFLOP/s",
+                "frac": round(tf / peak_alu, 4), "traffic": None}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None}
+    roof["per_stage"] = {"alg_flops": flops, "alg_bytes": byts, "duration_us": round(t_stage * 1e6, 3),
+                         "other_bound": ({"hbm_GBs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
+                                         if roof["bound"] == "alu" else
+                                         {"alu_TFLOPs": round(tf, 3), "frac": round(tf / peak_alu, 4)})}
+    trace = os.path.join(ROOT, "profiles", "stage_kernel_ensemble_256.md")
+    if args.ensemble == 256 and not args.matrix_cores and not wadg and os.path.exists(trace):
+        roof["per_stage"]["duration_source"] = ("HIP events on the solver stream over the timed steps, per RK "
+                                                "stage (rocprofv3 kernel trace of this workload: "
+                                                "profiles/stage_kernel_ensemble_256.md)")
+    out["roofline"] = roof
     print(json.dumps(out), flush=True)
 
 
