@@ -13,7 +13,7 @@ follows.  It evaluates the *literal dense* semi-discrete form, eq. (dgform) of
 Section 2.8, with the Lax-Friedrichs penalty of Section 2.8 and the five-stage
 low-storage RK4 of Section 4, in float64, vectorised over elements with numpy.
 
-Readings where the paper is silent, garbled or ambiguous (all listed in the design doc):
+Readings where the paper is silent, garbled or ambiguous:
 
 * modal basis (Section 2.1 leaves it open): orthonormal Dubiner (PKDO) basis,
   modes ordered ``for i in 0..N: for j in 0..N-i``;

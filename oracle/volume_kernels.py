@@ -2,7 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY.  The plain definitions the HIP micro-benchmark kernels are checked
 against (and, through the C versions in volume_kernels.c, the CPU side of the cost ratio).
-Only ``tests/`` and ``bench.py`` use this module; the library never does.
+Only ``tests/`` and ``bench.py``'s CPU-baseline leg of the volume-kernel ratio (skipped by
+--no-cpu-baseline) use this module; the library never does.
 
 Section 5.4 compares the volume term of a traditional DG scheme, a matrix-vector product
 of a differentiation-type matrix with the flux evaluated at each node, against the
