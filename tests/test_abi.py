@@ -131,3 +131,35 @@ def test_init_walls():
         assert st == expect, lib.esdg_swe_last_error(None).decode()
         if st == binding.ESDG_OK:
             lib.esdg_swe_destroy(h)
+
+
+def test_empty_and_out_of_range_inputs():
+    """Empty inputs and sizes outside the documented ranges are rejected at the boundary,
+    before any device call: no instances, an instance of 0 elements, degrees 0 and 6, more
+    than 64 elements per workgroup; the volume-kernel entry point with 0 elements, 0 or 257
+    nodes, or an unknown kind."""
+    lib = binding.load_library()
+    w = wl.config2(n=2, N=2)
+    xg, yg, b = (np.ascontiguousarray(a) for a in (w.xg, w.yg, w.b_nodes))
+
+    def init(N, K, n_inst=1, epb=0):
+        arr = (binding.esdg_swe_instance * 1)()
+        arr[0] = binding.esdg_swe_instance(N, K, binding._dptr(xg), binding._dptr(yg), binding._dptr(b), w.Lx, w.Ly)
+        opt = binding.make_options("fp32", "lf", 1.0, True, epb)
+        h, nb = C.c_void_p(), C.c_size_t()
+        st = lib.esdg_swe_init(n_inst, arr, C.byref(opt), C.byref(h), C.byref(nb))
+        if st == binding.ESDG_OK:
+            lib.esdg_swe_destroy(h)
+        return st
+
+    assert init(2, w.K) == binding.ESDG_OK
+    assert init(2, w.K, n_inst=0) == binding.ESDG_EINVAL
+    assert init(2, 0) == binding.ESDG_EINVAL
+    assert init(0, w.K) == binding.ESDG_EINVAL
+    assert init(6, w.K) == binding.ESDG_EINVAL
+    assert init(2, w.K, epb=65) == binding.ESDG_EINVAL
+    dummy = C.c_void_p(16)                   # never dereferenced: the checks come first
+    for kind, prec, n, K in ((0, binding.ESDG_FP32, 10, 0), (0, binding.ESDG_FP32, 0, 4),
+                             (1, binding.ESDG_FP64, 257, 4), (2, binding.ESDG_FP32, 10, 4)):
+        assert lib.esdg_volume_kernel(kind, prec, dummy, dummy, dummy, dummy, n, K, C.c_double(9.81), None) \
+            == binding.ESDG_EINVAL, (kind, n, K)
