@@ -33,8 +33,9 @@ def test_lookup_size_classes():
     assert A.lookup("fp32", [(3, 8192)]) == {3: c["fp32:N3:S"]["epb"]}
     assert A.lookup("fp32", [(1, 65522)]) == {1: c["fp32:N1:M"]["epb"]}
     assert A.lookup("fp64", [(1, 65522)]) == {1: c["fp64:N1:M"]["epb"]}
-    # no large-mesh class is tuned: the nearest one (M) serves it
-    assert A.lookup("fp32", [(5, 524288)]) == {5: c["fp32:N5:M"]["epb"]}
+    assert A.lookup("fp32", [(5, 524288)]) == {5: c["fp32:N5:L"]["epb"]}
+    # no large-mesh class at N=4: the nearest one (M) serves it
+    assert A.lookup("fp32", [(4, 524288)]) == {4: c["fp32:N4:M"]["epb"]}
     # the split-bf16 mode has the float LDS footprint
     assert A.lookup("bf16x3", [(5, 524288)]) == A.lookup("fp32", [(5, 524288)])
     # instances of one degree add up before the class is picked
