@@ -134,6 +134,45 @@ def test_wadg_fused_steps_bitwise(torch, precision):
     assert np.array_equal(out[0], out[1])
 
 
+MC_MODES = {"bf16x3": ("bf16x3", {}, 2.0 ** -16), "fp32_mfma": ("fp32", {"matrix_cores": True}, EPS32),
+            "fp64_mfma": ("fp64", {"matrix_cores": True}, EPS64)}
+
+
+@pytest.mark.parametrize("N,n", [(3, 4), (5, 2)])
+@pytest.mark.parametrize("mode", list(MC_MODES))
+def test_rhs_wadg_matrix_cores(torch, N, n, mode):
+    """The weight-adjusted inverse with the other contractions on the matrix cores (split-bf16,
+    or in the bulk precision); its own two passes run on the vector ALUs in every mode.  One
+    RHS within 64 eps of the rounding bound (eps_eff = 2^-16 for split-bf16), and 3 steps of
+    the multi-stage launch bitwise equal to per-stage launches."""
+    prec, kw, eps = MC_MODES[mode]
+    w = wl.config2(n=n, N=N)
+    u = w.u_nodes.copy()
+    rng = np.random.default_rng(7)
+    u[1] += 0.1 * u[0] * rng.uniform(-1, 1, u[0].shape)
+    u[2] += 0.1 * u[0] * rng.uniform(-1, 1, u[0].shape)
+    s = solver(w, prec, "lf", **kw)
+    s.set_state(0, u)
+    uh = s.get_state(0)
+    st = s.state_device(0)
+    rhs = torch.empty_like(st)
+    s.rhs(0, st, rhs)
+    s.sync()
+    s.close()
+    d, o = wadg_oracle(w, "lf", uh)
+    ok, worst = check_rhs(rhs.cpu().double().numpy(), o.rhs(uh), rhs_abs_bound(o, uh, np.arange(w.K)), eps)
+    print(f"wadg {mode} N={N}: worst err / (eps * bound) = {worst:.3f}", flush=True)
+    assert ok, worst
+    out = []
+    for fused in (False, True):
+        s = solver(w, prec, "lf", fused=fused, **kw)
+        s.set_state(0, w.u_nodes)
+        s.step(w.dt, 3)
+        out.append(s.get_state(0))
+        s.close()
+    assert np.array_equal(out[0], out[1])
+
+
 def test_wadg_entropy_conservation_gpu(torch):
     """EC flux on a curved periodic mesh: the entropy rate vanishes to round-off (it needs
     the same inverse in the projection and the lift); LF makes it negative."""
