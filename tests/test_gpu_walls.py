@@ -214,3 +214,30 @@ def test_walls_in_mixed_ensemble(torch):
         hn = np.linalg.norm(ur[0])
         err = max(np.linalg.norm(u[c] - ur[c]) / hn for c in range(3))
         assert err < 1e-12, (w.name, w.N, err)
+
+
+@pytest.mark.parametrize("mode", ["bf16x3", "fp32_mfma", "fp64_mfma"])
+def test_walls_matrix_cores(torch, mode):
+    """Walls with the projection and lift contractions on the matrix cores (split-bf16, or in
+    the bulk precision): one RHS within 64 eps of the rounding bound (eps_eff = 2^-16 for
+    split-bf16), and 3 steps of the multi-stage launch bitwise equal to per-stage launches."""
+    prec, kw, eps = {"bf16x3": ("bf16x3", {}, 2.0 ** -16), "fp32_mfma": ("fp32", {"matrix_cores": True}, EPS32),
+                     "fp64_mfma": ("fp64", {"matrix_cores": True}, EPS64)}[mode]
+    w = moving_basin(3, 3)
+    s = solver(w, prec, "lf", **kw)
+    s.set_state(0, w.u_nodes)
+    uh = s.get_state(0)
+    r = rhs_of(torch, s)
+    s.close()
+    d, o = oracle_for(w, "lf")
+    ok, worst = check_rhs(r, o.rhs(uh), rhs_abs_bound(o, uh, np.arange(w.K)), eps)
+    print(f"walls {mode}: worst err / (eps * bound) = {worst:.3f}", flush=True)
+    assert ok, worst
+    out = []
+    for fused in (False, True):
+        s = solver(w, prec, "lf", fused=fused, **kw)
+        s.set_state(0, w.u_nodes)
+        s.step(w.dt, 3)
+        out.append(s.get_state(0))
+        s.close()
+    assert np.array_equal(out[0], out[1])
