@@ -737,6 +737,10 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
     }
   } else {
     if (!wait_neighbours(a, t, target)) return false;
+    // from here to its publish the tile is on its neighbours' critical path (their next
+    // stage waits for its pushes), while the other workgroups on the CU that are still in
+    // their pair loop have slack: raise this workgroup's wave priority until the publish
+    __builtin_amdgcn_s_setprio(2);
     async_copy_words<kCpolAgent>(reinterpret_cast<uint32_t *>(L.nb),
                                  static_cast<const uint32_t *>(d.nbx[a.in_buf]) + size_t(k0) * Nfq * 4 * W,
                                  ne * Nfq * 4 * W);
@@ -888,7 +892,10 @@ stage_kernel(StageArgs a) {
         if (threadIdx.x == 0) atomicOr(a.flag, 2);
         return;
       }
-      if (multi) publish(a, t, a.stage0 + s + 1);
+      if (multi) {
+        publish(a, t, a.stage0 + s + 1);
+        __builtin_amdgcn_s_setprio(0);
+      }
       else __syncthreads();
     }
   }
