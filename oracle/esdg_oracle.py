@@ -525,7 +525,7 @@ class Oracle:
         vh = d.project(vq)
         vt = vh @ ref.Vh.T
         vt[0] += g * self.Href
-        vh[:, :, 0] += g * self.Href * math.sqrt(2.0)          # the constant 1 is sqrt(2) phi_0
+        vh[0, :, 0] += g * self.Href * math.sqrt(2.0)          # depth field only; 1 = sqrt(2) phi_0
         ut = np.stack(conservative_from_entropy(vt[0], vt[1], vt[2], d.b_hyb, g))
         return ut, vh
 

@@ -108,3 +108,27 @@ def test_source_sign_flip_caught(monkeypatch):
     monkeypatch.setattr(O.Oracle, "residual", flipped)
     d, u, lake = _setup()
     assert not properties_hold(d, u, lake)
+
+
+def _vh_consistent(d, u, Href):
+    """V_h v_h equals the entropy variables of u~ (both from entropy_projection)."""
+    ut, vh = O.Oracle(d, "lf", Href=Href).entropy_projection(d.interpolate(u))
+    v = np.stack(O.entropy_variables(ut[0], ut[1], ut[2], d.b_hyb, d.g))
+    return np.abs(vh @ d.ref.Vh.T - v).max() < 1e-12 * np.abs(v).max()
+
+
+def test_reference_level_shift_on_momentum_caught(monkeypatch):
+    """Shifting the projected momentum variables by the reference level as well as the depth
+    variable breaks V_h v_h = v(u~)."""
+    real = O.Oracle.entropy_projection
+
+    def shifted(self, uh):
+        ut, vh = real(self, uh)
+        vh = vh.copy()
+        vh[1:, :, 0] += self.d.g * self.Href * np.sqrt(2.0)
+        return ut, vh
+
+    d, u, _ = _setup()
+    assert _vh_consistent(d, u, 2.2)
+    monkeypatch.setattr(O.Oracle, "entropy_projection", shifted)
+    assert not _vh_consistent(d, u, 2.2)
