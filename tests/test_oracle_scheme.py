@@ -406,9 +406,9 @@ def _vortex_error(N, n, T=0.1):
                                           (3, (8, 16), 3.5)])
 def test_vortex_convergence(N, ns, minrate):
     """PIN-13 (Section 4.2): L2 error of the translating vortex on curved meshes falls at
-    about h^(N+1) for odd N (N=3: at least N+1/2 = 3.5, measured 3.7-4.0 from 8x8x2 to
-    16x16x2); for even N on these structured meshes it settles at h^(N+1/2) (N=2: 2.45-2.7
-    on three successive refinements, not rising towards 3)."""
+    about h^(N+1) (N=3: at least N+1/2 = 3.5, measured 3.7-4.0 from 8x8x2 to 16x16x2).  For
+    N=2 the coarse levels are pre-asymptotic: 2.45-2.68 per field from 8 to 16 and from 16
+    to 32 squares per side, 2.61-2.93 from 32 to 64 (not run here), rising towards 3."""
     e0 = _vortex_error(N, ns[0])
     e1 = _vortex_error(N, ns[1])
     rate = np.log2(e0 / e1)
