@@ -182,6 +182,20 @@ esdg_status esdg_swe_state_device(esdg_swe *s, int32_t inst, void **uh_dev);
  * not overlap. */
 esdg_status esdg_swe_rhs(esdg_swe *s, int32_t inst, const void *state_dev, void *rhs_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): esdg_swe_rhs without the workspace's
+ * RHS scratch.  Same arguments, kernels and results (bitwise) as esdg_swe_rhs; the
+ * entropy-projected values and face slots of the evaluation, and its non-physical-state
+ * flag, live in a scratch array the library holds per device (64 MiB, kept until the process
+ * ends), and the call allocates nothing.  The instance needs
+ *   256 + round_up(16 K Nh w, 256) + 16 K Nfq w   bytes of it (w = 4 for float, 8 for double;
+ * N=3, K=8192: 5.3 MB in FP32); a larger one returns ESDG_EINVAL (use esdg_swe_rhs).
+ * Asynchronous on the bound stream; a non-physical state is reported by the handle's next
+ * synchronising call.  Every handle on a device shares that device's array, which keeps the
+ * last call's contents: calls that overlap in time on one device (two streams, two handles,
+ * two threads) race and give undefined results. */
+esdg_status esdg_swe_rhs_noalloc(esdg_swe *s, int32_t inst, const void *state_dev, void *rhs_dev);
+
 /* Advance every instance by nsteps LSRK4(5) steps (5 RHS evaluations each, Section 4).
  * dt is a host array with one time step per instance.  Asynchronous on the bound stream:
  * one kernel launch per RK stage for all instances together, replayed from HIP graphs

@@ -23,7 +23,7 @@ FLUXES = {"ec": ESDG_FLUX_EC, "lf": ESDG_FLUX_LF}
 
 EXPORTED = [
     "esdg_swe_init", "esdg_swe_bind", "esdg_swe_set_state", "esdg_swe_set_state_modal", "esdg_swe_get_state",
-    "esdg_swe_state_device", "esdg_swe_rhs", "esdg_swe_step", "esdg_swe_diagnostics", "esdg_swe_sync",
+    "esdg_swe_state_device", "esdg_swe_rhs", "esdg_swe_rhs_noalloc", "esdg_swe_step", "esdg_swe_diagnostics", "esdg_swe_sync",
     "esdg_swe_query", "esdg_swe_launch_info", "esdg_swe_reference_level", "esdg_swe_last_error", "esdg_swe_destroy",
     "esdg_volume_kernel",
 ]
@@ -89,6 +89,7 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
     lib.esdg_swe_get_state.argtypes = [vp, i32, pdbl]
     lib.esdg_swe_state_device.argtypes = [vp, i32, C.POINTER(vp)]
     lib.esdg_swe_rhs.argtypes = [vp, i32, vp, vp]
+    lib.esdg_swe_rhs_noalloc.argtypes = [vp, i32, vp, vp]
     lib.esdg_swe_step.argtypes = [vp, pdbl, i32]
     lib.esdg_swe_diagnostics.argtypes = [vp, pdbl]
     lib.esdg_swe_sync.argtypes = [vp]
@@ -212,6 +213,14 @@ class EsdgSwe:
             assert t.is_cuda and t.dtype == self.dtype and t.is_contiguous() and tuple(t.shape) == (3, z["K"], z["Np"])
         self._check(self.lib.esdg_swe_rhs(self.h, inst, C.c_void_p(state.data_ptr()), C.c_void_p(rhs.data_ptr())))
 
+    def esdg_swe_rhs_noalloc(self, inst: int, state, rhs):
+        """esdg_swe_rhs with its scratch in the library's per-device array (no allocation)."""
+        z = self.sizes[inst]
+        for t in (state, rhs):
+            assert t.is_cuda and t.dtype == self.dtype and t.is_contiguous() and tuple(t.shape) == (3, z["K"], z["Np"])
+        self._check(self.lib.esdg_swe_rhs_noalloc(self.h, inst, C.c_void_p(state.data_ptr()),
+                                                  C.c_void_p(rhs.data_ptr())))
+
     def esdg_swe_step(self, dt, nsteps: int):
         d = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (self.n_inst,)))
         self._check(self.lib.esdg_swe_step(self.h, _dptr(d), int(nsteps)))
@@ -230,6 +239,7 @@ class EsdgSwe:
     get_state = esdg_swe_get_state
     state_device = esdg_swe_state_device
     rhs = esdg_swe_rhs
+    rhs_noalloc = esdg_swe_rhs_noalloc
     step = esdg_swe_step
     diagnostics = esdg_swe_diagnostics
     sync = esdg_swe_sync

@@ -119,6 +119,9 @@ struct StageArgs {
   double rk_a, rk_b;
   const void *ext_state;  // kProject: read this state instead of desc.uh (when non-null)
   void *ext_rhs;          // kRhs: write here
+  void *ext_ut;           // kProject / kRhs: the projected values and the face slots of this
+  void *ext_nbx;          // launch in these buffers instead of desc.ut / desc.nbx (when non-null;
+                          // one instance per launch, layouts as desc.ut[b] and desc.nbx[b])
   int32_t *flag;          // bit 0: a non-physical value was seen; bit 1: a neighbour wait timed out
   // Multi-stage launch (progress != null; all workgroups co-resident): nstages kStage stages
   // starting at global stage index stage0, buffers alternating from in_buf, coefficients

@@ -459,7 +459,8 @@ __device__ __forceinline__ void fetch_tile(const StageArgs &a, const InstDesc &d
   if (a.mode != kProject) {
     // u~ and the metric factors are stored tile-blocked ([4][ne][Nh] per tile), one copy each
     const size_t base = size_t(k0) * 4 * Nh;
-    async_copy_words(lwords(L.raw), words(static_cast<const real *>(d.ut[a.in_buf]) + base), 4 * ne * Nh * W);
+    const void *ut = a.ext_ut ? a.ext_ut : d.ut[a.in_buf];
+    async_copy_words(lwords(L.raw), words(static_cast<const real *>(ut) + base), 4 * ne * Nh * W);
     async_copy_words(lwords(L.raw + 4 * ne * Nh), words(static_cast<const real *>(d.geo) + base), 4 * ne * Nh * W);
   }
   if (a.mode == kStage) {
@@ -484,7 +485,8 @@ __device__ __forceinline__ void fetch_tile(const StageArgs &a, const InstDesc &d
                      nstat - head);
   }
   if (a.mode != kProject) {        // neighbour values, pushed here by the neighbours' projections
-    const uint32_t *src = words(static_cast<const real *>(d.nbx[a.in_buf]) + size_t(k0) * Nfq * 4);
+    const void *nbx = a.ext_nbx ? a.ext_nbx : d.nbx[a.in_buf];
+    const uint32_t *src = words(static_cast<const real *>(nbx) + size_t(k0) * Nfq * 4);
     if (MULTI && a.progress)       // multi-stage launch: written during this kernel, maybe on another XCD
       async_copy_words<kCpolAgent>(lwords(L.nb), src, ne * Nfq * 4 * W);
     else
@@ -711,8 +713,9 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
   }
   if (a.mode == kProject) {
     __syncthreads();
-    project_tile<real, N, CM, WADG>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]),
-                              static_cast<real *>(d.nbx[a.out_buf]), a.flag, MULTI && a.progress != nullptr);
+    project_tile<real, N, CM, WADG>(d, k0, ne, L, static_cast<real *>(a.ext_ut ? a.ext_ut : d.ut[a.out_buf]),
+                              static_cast<real *>(a.ext_nbx ? a.ext_nbx : d.nbx[a.out_buf]), a.flag,
+                              MULTI && a.progress != nullptr);
     return true;
   }
   __syncthreads();

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -38,6 +39,46 @@ const double kRkB[5] = {1432997174477.0 / 9575080441904.0, 5161836677717.0 / 136
                         2277821191437.0 / 14882151754819.0};
 
 thread_local std::string g_init_error;
+
+// Scratch of esdg_swe_rhs_noalloc (callers that cannot allocate device memory): a flag word,
+// then the entropy-projected values and the face slots of the one instance it evaluates.
+// Each device that loads the library holds its own copy until the process ends; host code
+// uses only the device address returned by hipGetSymbolAddress (kept per device), never the
+// array's name, which on the host is a stand-in and not a device address.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr size_t kScratchHead = 256;       // flag word (int32), padded to the 256-byte alignment
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (resolved once per device).
+hipError_t scratch_address(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// Bytes of scratch one no-allocation RHS evaluation of an instance needs.
+size_t noalloc_bytes(int N, int K, size_t word) {
+  const size_t ut = (size_t(4) * K * dim_Nh(N) * word + 255) & ~size_t(255);
+  return kScratchHead + ut + size_t(4) * K * dim_Nfq(N) * word;
+}
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -91,6 +132,8 @@ struct esdg_swe {
   bool bound = false;
   std::vector<bool> state_set;
   int parity = 0;                  // which ut buffer holds the projection of the current state
+  void *scratch_dev = nullptr;     // the bound device's scratch array (esdg_swe_rhs_noalloc)
+  bool scratch_used = false;       // an esdg_swe_rhs_noalloc call may have set its flag word
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (steps, start parity) -> exec
   std::string err;
 
@@ -179,6 +222,18 @@ esdg_status check_flag(esdg_swe *s) {
   int32_t flag = 0;
   e = hipMemcpy(&flag, s->dev<int32_t>(s->flag_off), sizeof flag, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return s->hip_fail(e, "hipMemcpy (flag)");
+  if (s->scratch_used) {           // the no-allocation RHS reports into the scratch flag word
+    int32_t f2 = 0;
+    e = hipMemcpy(&f2, s->scratch_dev, sizeof f2, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return s->hip_fail(e, "hipMemcpy (scratch flag)");
+    if (f2) {
+      const int32_t zero = 0;
+      e = hipMemcpy(s->scratch_dev, &zero, sizeof zero, hipMemcpyHostToDevice);
+      if (e != hipSuccess) return s->hip_fail(e, "hipMemcpy (scratch flag reset)");
+    }
+    s->scratch_used = false;
+    flag |= f2;
+  }
   if (flag) {
     int32_t zero = 0;
     (void)hipMemcpy(s->dev<int32_t>(s->flag_off), &zero, sizeof zero, hipMemcpyHostToDevice);
@@ -378,6 +433,10 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
   if (reinterpret_cast<uintptr_t>(dev_workspace) % 256) return s->fail(ESDG_EINVAL, "bind: workspace not 256-byte aligned");
   s->ws = static_cast<unsigned char *>(dev_workspace);
   s->stream = static_cast<hipStream_t>(hip_stream);
+  {
+    hipError_t e = scratch_address(&s->scratch_dev);
+    if (e != hipSuccess) return s->hip_fail(e, "hipGetSymbolAddress (scratch)");
+  }
   if (s->lds_bytes > 64 * 1024) {
     hipError_t e = set_stage_lds_limit(s->fp64, s->contraction, s->wadg, s->lds_bytes);
     if (e != hipSuccess) return s->hip_fail(e, "hipFuncSetAttribute (LDS)");
@@ -592,6 +651,36 @@ esdg_status esdg_swe_rhs(esdg_swe *s, int32_t inst, const void *state_dev, void 
   if (st) return st;
   a.mode = kRhs;
   a.in_buf = 2;
+  a.ext_state = nullptr;
+  a.ext_rhs = rhs_dev;
+  return launch(s, a, a.ntiles);
+}
+
+esdg_status esdg_swe_rhs_noalloc(esdg_swe *s, int32_t inst, const void *state_dev, void *rhs_dev) {
+  if (!s) return ESDG_EINVAL;
+  if (!s->bound) return s->fail(ESDG_ESTATE, "rhs_noalloc before bind");
+  if (inst < 0 || inst >= s->n_inst || !state_dev || !rhs_dev) return s->fail(ESDG_EINVAL, "rhs_noalloc: bad arguments");
+  if (!s->state_set[inst]) return s->fail(ESDG_ESTATE, "rhs_noalloc: set_state first (defines the pressure reference level)");
+  const InstanceHost &H = s->host[inst];
+  const size_t bytes = size_t(3) * H.K * dim_Np(H.N) * s->word;
+  const char *a0 = static_cast<const char *>(state_dev), *b0 = static_cast<const char *>(rhs_dev);
+  if (a0 < b0 + bytes && b0 < a0 + bytes) return s->fail(ESDG_EINVAL, "rhs_noalloc: state and rhs overlap");
+  const size_t need = noalloc_bytes(H.N, H.K, s->word);
+  if (need > kScratchBytes)
+    return s->fail(ESDG_EINVAL, "rhs_noalloc: the instance needs " + std::to_string(need) +
+                                    " bytes of scratch, more than the " + std::to_string(kScratchBytes) +
+                                    " the library holds per device (use esdg_swe_rhs)");
+  unsigned char *base = static_cast<unsigned char *>(s->scratch_dev);
+  StageArgs a = base_args(s, inst);
+  a.flag = reinterpret_cast<int32_t *>(base);
+  a.ext_ut = base + kScratchHead;
+  a.ext_nbx = base + kScratchHead + ((size_t(4) * H.K * dim_Nh(H.N) * s->word + 255) & ~size_t(255));
+  a.mode = kProject;
+  a.ext_state = state_dev;
+  s->scratch_used = true;
+  esdg_status st = launch(s, a, a.ntiles);
+  if (st) return st;
+  a.mode = kRhs;
   a.ext_state = nullptr;
   a.ext_rhs = rhs_dev;
   return launch(s, a, a.ntiles);

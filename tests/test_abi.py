@@ -88,6 +88,8 @@ def test_calls_before_bind_fail_cleanly():
     assert lib.esdg_swe_step(h, binding._dptr(dt), 1) == binding.ESDG_ESTATE
     u = np.ascontiguousarray(w.u_nodes)
     assert lib.esdg_swe_set_state(h, 0, binding._dptr(u)) == binding.ESDG_ESTATE
+    assert lib.esdg_swe_rhs(h, 0, u.ctypes.data, u.ctypes.data) == binding.ESDG_ESTATE
+    assert lib.esdg_swe_rhs_noalloc(h, 0, u.ctypes.data, u.ctypes.data) == binding.ESDG_ESTATE
     lib.esdg_swe_destroy(h)
 
 
