@@ -235,8 +235,10 @@ esdg_status esdg_swe_launch_info(const esdg_swe *s, int32_t *out4);
 /* Message for the last failing call on s (s may be NULL: last failing init on this thread). */
 const char *esdg_swe_last_error(const esdg_swe *s);
 
-/* Release host resources of the handle (HIP graphs included).  The workspace and stream
- * remain the caller's.  NULL is ignored. */
+/* Wait for the work queued on the bound stream (a replay of the handle's HIP graphs or a
+ * cooperative launch may still read the workspace), then release the handle's host
+ * resources (HIP graphs included).  The workspace and stream remain the caller's and may be
+ * freed once this returns.  NULL is ignored. */
 void esdg_swe_destroy(esdg_swe *s);
 
 #ifdef __cplusplus

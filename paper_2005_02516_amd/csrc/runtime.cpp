@@ -138,6 +138,9 @@ struct esdg_swe {
   std::string err;
 
   ~esdg_swe() {
+    // work still queued on the stream may be a replay of one of these graphs, or a
+    // cooperative launch reading the workspace: let it finish before anything is released
+    if (bound) (void)hipStreamSynchronize(stream);
     for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
   }
   template <typename T>
