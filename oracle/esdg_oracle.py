@@ -35,7 +35,12 @@ Readings where the paper is silent, garbled or ambiguous:
 * LSRK coefficients: the published Carpenter-Kennedy (1994) 2N-storage values;
 * optional weight-adjusted mass inverse (the implementation remark after eq. (dgform),
   Section 2.8): M^{-1} M_{1/J} M^{-1} in both the entropy projection and the lift, with
-  the projected entropy variables those of S - g Href h (Href a fixed reference level).
+  the projected entropy variables those of S - g Href h (Href a fixed reference level);
+* optional quadrature (Section 2.1 fixes only minimum degrees): the Stroud rule with more
+  points per direction, more Gauss-Legendre points per face, or a caller's volume rule;
+* the DG-SBP scheme of Section 3.2 (SBPOracle): the bathymetry source and the LF penalty
+  are those of the modal scheme, with the nodal values in place of the entropy-projected
+  ones, and the curved SBP mass matrix is W diag(J).
 """
 from __future__ import annotations
 
@@ -160,13 +165,15 @@ def dubiner(N: int, r: np.ndarray, s: np.ndarray, grad: bool = False):
     return V
 
 
-def stroud_rule(N: int):
-    """Volume rule: (N+1)-point Gauss-Legendre in a times (N+1)-point Gauss-Jacobi(1,0) in b.
+def stroud_rule(N: int, q: Optional[int] = None):
+    """Volume rule: q-point Gauss-Legendre in a times q-point Gauss-Jacobi(1,0) in b (q = N+1
+    by default).
 
     Collapsed map r = (1+a)(1-b)/2 - 1, s = b, weight w = w_a w_b / 2 (sum w = 2, the
-    reference area).  Exact for total degree 2N+1, which covers the 2N volume rule.
+    reference area).  Exact for total degree 2q-1 (2N+1 by default, which covers the 2N
+    volume rule of Section 2.1).
     """
-    q = N + 1
+    q = N + 1 if q is None else int(q)
     xa, wa = gauss_jacobi(q, 0.0, 0.0)
     xb, wb = gauss_jacobi(q, 1.0, 0.0)
     A, Bm = np.meshgrid(xa, xb, indexing="ij")
@@ -177,15 +184,16 @@ def stroud_rule(N: int):
     return r, s, w
 
 
-def face_rule(N: int):
-    """N+1 Gauss-Legendre points on each face, faces listed 1, 2, 3, each counter-clockwise.
+def face_rule(N: int, npts: Optional[int] = None):
+    """npts (default N+1) Gauss-Legendre points on each face, faces listed 1, 2, 3, each
+    counter-clockwise.
 
     Face 1: s=-1 from v1 to v2, scaled normal (0,-1).
     Face 2: r+s=0 from v2 to v3, scaled normal (1, 1) (unit normal times the face Jacobian sqrt 2).
     Face 3: r=-1 from v3 to v1, scaled normal (-1, 0).
     The weights are the Gauss-Legendre weights in the face parameter t in [-1, 1].
     """
-    t, wt = gauss_jacobi(N + 1, 0.0, 0.0)
+    t, wt = gauss_jacobi(N + 1 if npts is None else int(npts), 0.0, 0.0)
     rf = np.concatenate([t, -t, -np.ones_like(t)])
     sf = np.concatenate([-np.ones_like(t), t, -t])
     wf = np.concatenate([wt, wt, wt])
@@ -195,19 +203,57 @@ def face_rule(N: int):
     return rf, sf, wf, nr, ns
 
 
-class ReferenceElement:
-    """Reference-element operators of Sections 2.1-2.3 for degree N."""
+def quadrature_rules(N: int, quad: Optional[dict] = None):
+    """The volume and face rules of degree N selected by ``quad`` (Section 2.1 fixes only
+    minimum degrees): None gives the Stroud rule with N+1 points per direction and N+1
+    Gauss-Legendre points per face; a mapping may give "vol_degree" (the Stroud rule with
+    ceil((vol_degree+1)/2) points per direction, at least N+1), "face_points" (default N+1)
+    and "rule" = (r, s, w), a caller's volume rule used as given."""
+    quad = quad or {}
+    npf = int(quad.get("face_points") or N + 1)
+    if quad.get("rule") is not None:
+        r, s, w = (np.asarray(a, dtype=np.float64) for a in quad["rule"])
+    else:
+        deg = int(quad.get("vol_degree") or 2 * N)
+        r, s, w = stroud_rule(N, max(N + 1, (deg + 2) // 2))
+    return (r, s, w), face_rule(N, npf)
 
-    def __init__(self, N: int):
+
+def monomial_integral(a: int, b: int) -> float:
+    """Exact integral of r^a s^b over the reference triangle:
+    int_{-1}^{1} s^b ((-s)^(a+1) - (-1)^(a+1)) / (a+1) ds (rational arithmetic)."""
+    from fractions import Fraction
+    def pint(p):
+        return Fraction(0) if p % 2 else Fraction(2, p + 1)
+    sg = -1 if (a + 1) % 2 else 1
+    return float(Fraction(sg, a + 1) * (pint(a + b + 1) - pint(b)))
+
+
+def rule_degree(r, s, w, max_degree: int = 30, tol: float = 1e-13) -> int:
+    """Largest d such that the rule integrates every r^a s^b with a + b <= d exactly."""
+    d = -1
+    for deg in range(max_degree + 1):
+        for a in range(deg + 1):
+            b = deg - a
+            if abs(np.sum(w * r ** a * s ** b) - monomial_integral(a, b)) > tol * max(1.0, np.sum(np.abs(w))):
+                return d
+        d = deg
+    return d
+
+
+class ReferenceElement:
+    """Reference-element operators of Sections 2.1-2.3 for degree N (quadrature as selected
+    by ``quad``, see quadrature_rules)."""
+
+    def __init__(self, N: int, quad: Optional[dict] = None):
         self.N = N
         self.Np = n_modes(N)
-        rq, sq, wq = stroud_rule(N)
-        rf, sf, wf, nr, ns = face_rule(N)
+        (rq, sq, wq), (rf, sf, wf, nr, ns) = quadrature_rules(N, quad)
         self.rq, self.sq, self.wq = rq, sq, wq
         self.rf, self.sf, self.wf, self.nrJ, self.nsJ = rf, sf, wf, nr, ns
         self.Nq, self.Nfq = rq.size, rf.size
         self.Nh = self.Nq + self.Nfq
-        self.Nfp = N + 1
+        self.Nfp = self.Nfq // 3
         Vq, Vrq, Vsq = dubiner(N, rq, sq, grad=True)
         Vf, Vrf, Vsf = dubiner(N, rf, sf, grad=True)
         self.Vq, self.Vf = Vq, Vf
@@ -262,11 +308,11 @@ class Discretization:
     """
 
     def __init__(self, N: int, xg: np.ndarray, yg: np.ndarray, b_nodes: Optional[np.ndarray], g: float,
-                 Lx: float, Ly: float, mass: str = "exact"):
+                 Lx: float, Ly: float, mass: str = "exact", quad: Optional[dict] = None):
         if mass not in ("exact", "wadg"):
             raise ValueError("mass must be 'exact' or 'wadg'")
         self.mass = mass
-        ref = ReferenceElement(N)
+        ref = ReferenceElement(N, quad)
         self.ref, self.N, self.g = ref, N, float(g)
         self.K = xg.shape[0]
         self.Lx, self.Ly = float(Lx), float(Ly)
@@ -594,6 +640,96 @@ class Oracle:
 
 
 # ----------------------------------------------------------------------------------
+# DG-SBP scheme (Section 3): traditional SBP operators from the hybridized ones
+# ----------------------------------------------------------------------------------
+
+
+class SBPOracle:
+    """Dense FP64 evaluation of the entropy-conservative DG-SBP form at the end of Section
+    3.2, with the bathymetry source and the LF penalty of the modal scheme:
+
+        M_SBP du/dt + sum_i (2 Q_SBP^i o F^i) 1 + I_f^T B^i (f_S^i - f^i) = S,
+
+    with Q_SBP^i = [I; I_f]^T Q_h^i [I; I_f] (the theorem of Section 3.2) built from the
+    physical hybridized operator of Section 2.7 on the rule's nodes, I_f the selection of the
+    face nodes among the volume nodes, M_SBP^k = W diag(J) (the SBP mass matrix on curved
+    elements), u the nodal values at the volume nodes, F^i[m, n] = f_S^i(u_m, u_n) over the
+    volume nodes, and S = -g [0; diag(h) Q_SBP^x b; diag(h) Q_SBP^y b] with b at the volume
+    nodes.  The state has shape [3, K, Nq].  ``disc`` must be built with a volume rule
+    containing the face nodes (quad = {"rule": ..., "vol_degree": 2N-1}).
+    """
+
+    def __init__(self, disc: "Discretization", flux: str = "lf"):
+        if flux not in ("ec", "lf"):
+            raise ValueError("flux must be 'ec' or 'lf'")
+        self.d, self.flux = disc, flux
+        self.modal = Oracle(disc, flux)        # for the physical hybridized operators
+        ref = disc.ref
+        # I_f: face node f is volume node If[f] (same reference point)
+        dist = np.hypot(ref.rf[:, None] - ref.rq[None, :], ref.sf[:, None] - ref.sq[None, :])
+        self.If = np.argmin(dist, axis=1)
+        if np.max(dist[np.arange(ref.Nfq), self.If]) > 1e-12:
+            raise ValueError("the volume rule does not contain the face nodes")
+        self.sel = np.vstack([np.eye(ref.Nq), np.eye(ref.Nq)[self.If]])   # [I; I_f], Nh x Nq
+
+    def nodal(self, uh: np.ndarray) -> np.ndarray:
+        """Values at the volume nodes of the modal coefficients uh (the initial state)."""
+        return uh @ self.d.ref.Vq.T
+
+    def Q_sbp(self, ks):
+        """Q_SBP^{x,k}, Q_SBP^{y,k} of the elements ks, each [len(ks), Nq, Nq]."""
+        Qx_h, Qy_h = self.modal.physical_Qh(ks)
+        P = self.sel
+        return P.T @ Qx_h @ P, P.T @ Qy_h @ P
+
+    def rhs(self, u: np.ndarray) -> np.ndarray:
+        d, ref, g = self.d, self.d.ref, self.d.g
+        K = d.K
+        ks = np.arange(K)
+        Qx, Qy = self.Q_sbp(ks)
+        uL = tuple(u[c][:, :, None] for c in range(3))
+        uR = tuple(u[c][:, None, :] for c in range(3))
+        Fx, Fy = ec_flux(uL, uR, g)
+        r = np.zeros_like(u)
+        for c in range(3):
+            r[c] = 2.0 * np.sum(Qx * Fx[c] + Qy * Fy[c], axis=2)
+        bq = d.b_q
+        r[1] += g * u[0] * np.einsum("kmn,kn->km", Qx, bq)
+        r[2] += g * u[0] * np.einsum("kmn,kn->km", Qy, bq)
+        # I_f^T B (f_S(u+, u_f) - f(u_f)) and the LF penalty, at the face nodes
+        uh = u[:, :, np.r_[np.arange(ref.Nq), self.If]]          # values at the hybridized nodes
+        uf = uh[:, :, ref.Nq:]
+        up = exterior_state(d, uh, ks)
+        fS_x, fS_y = ec_flux(tuple(up), tuple(uf), g)
+        f_x, f_y = physical_flux(uf[0], uf[1], uf[2], g)
+        wf = ref.wf[None, :]
+        surf = np.zeros_like(uf)
+        for c in range(3):
+            surf[c] = wf * (d.nJx * (fS_x[c] - f_x[c]) + d.nJy * (fS_y[c] - f_y[c]))
+        if self.flux == "lf":
+            nx, ny = d.nJx / d.sJ, d.nJy / d.sJ
+            def speed(v):
+                return np.abs((v[1] * nx + v[2] * ny) / v[0]) + np.sqrt(g * v[0])
+            lam = np.maximum(speed(uf), speed(up))
+            for c in range(3):
+                surf[c] -= wf * 0.5 * lam * d.sJ * (up[c] - uf[c])
+        for c in range(3):
+            r[c] += surf[c] @ np.eye(ref.Nq)[self.If]                # I_f^T
+        return -r / (ref.wq[None, :] * d.Jq)[None]
+
+    def diagnostics(self, u: np.ndarray) -> Dict[str, float]:
+        """Mass sum w J h, entropy sum w J S(u), entropy rate sum w J v(u).du/dt."""
+        d, ref, g = self.d, self.d.ref, self.d.g
+        wJ = ref.wq[None, :] * d.Jq
+        dudt = self.rhs(u)
+        v = entropy_variables(u[0], u[1], u[2], d.b_q, g)
+        terms = wJ[None] * np.stack(v) * dudt
+        return {"mass": np.array([np.sum(wJ * u[c]) for c in range(3)]),
+                "entropy": float(np.sum(wJ * entropy(u[0], u[1], u[2], d.b_q, g))),
+                "entropy_rate": float(np.sum(terms)), "entropy_rate_scale": float(np.sum(np.abs(terms)))}
+
+
+# ----------------------------------------------------------------------------------
 # Time stepping (Section 4: five-stage fourth-order low-storage RK)
 # ----------------------------------------------------------------------------------
 
@@ -622,7 +758,7 @@ def lsrk_step(rhs, u: np.ndarray, du: np.ndarray, dt: float):
     return u, du
 
 
-def run(oracle: Oracle, uh: np.ndarray, dt: float, nsteps: int):
+def run(oracle, uh: np.ndarray, dt: float, nsteps: int):
     du = np.zeros_like(uh)
     u = uh.copy()
     for _ in range(nsteps):
