@@ -21,19 +21,22 @@
  *       phi_ij(r,s) = sqrt(2) P~_i(a) P~_j^{(2i+1,0)}(b) (1-b)^i,
  *       a = 2(1+r)/(1-s) - 1, b = s, P~ orthonormal Jacobi polynomials,
  *     modes ordered "for i in 0..N: for j in 0..N-i".
- *   - Quadrature: (N+1)^2-point Stroud collapsed rule (Gauss-Legendre x
- *     Gauss-Jacobi(1,0), exact to degree 2N+1) and N+1 Gauss-Legendre points per face.
+ *   - Quadrature (Section 2.1 fixes only minimum degrees): by default the (N+1)^2-point
+ *     Stroud collapsed rule (Gauss-Legendre x Gauss-Jacobi(1,0), exact to degree 2N+1) and
+ *     N+1 Gauss-Legendre points per face; esdg_swe_quadrature selects another (below).
  *   - Geometry / sampling nodes: order-N equispaced nodes listed
  *       "for j in 0..N: for i in 0..N-j: (r,s) = (-1 + 2i/N, -1 + 2j/N)"
  *     (node 0 = v1, node N = v2, last node = v3).  Each element is the
  *     isoparametric degree-N map through its nodes.
- *   - Np = (N+1)(N+2)/2.  State layout everywhere: [3][K][Np], element-major planes, modes
- *     fastest.  Host-side states (set_state*, get_state) hold (h, hu, hv).  Device-side
+ *   - Np = (N+1)(N+2)/2 (the number of modes), except for the DG-SBP scheme, whose state is
+ *     nodal: Np = Nq there.  State layout everywhere: [3][K][Np], element-major planes, modes
+ *     (or nodes) fastest.  Host-side states (set_state*, get_state) hold (h, hu, hv).  Device-side
  *     states (esdg_swe_state_device, esdg_swe_rhs) hold (eta, hu, hv) with the depth
  *     carried as the free-surface anomaly eta = h + b - Href, Href the instance's
  *     reference level (esdg_swe_reference_level): the modal coefficients of eta are those
- *     of h plus those of b minus Href*sqrt(2) on mode 0 (the constant 1 is sqrt(2) phi_00).
- *     The time derivative of eta equals that of h.
+ *     of h plus those of b minus Href*sqrt(2) on mode 0 (the constant 1 is sqrt(2) phi_00);
+ *     for DG-SBP the nodal values of h plus those of b minus Href.  The time derivative of
+ *     eta equals that of h.
  *
  * Ownership: the caller owns every host array passed in and may free it once the call
  * returns.  The caller owns the device workspace and the HIP stream given to
@@ -102,6 +105,35 @@ enum {
                                      conserved only to the accuracy of the weight adjustment. */
 };
 
+/* scheme (esdg_swe_options.scheme) */
+enum {
+  ESDG_SCHEME_MODAL = 0,  /* modal ESDG with hybridized SBP operators (Section 2)              */
+  ESDG_SCHEME_SBP = 1     /* DG-SBP with traditional SBP operators built from the hybridized
+                             ones (Section 3.2): nodal state at the volume nodes of a rule whose
+                             boundary nodes are the face nodes, diagonal mass matrix W J, no
+                             entropy projection; per-stage launches only                       */
+};
+
+/* Quadrature of one instance (Section 2.1: volume rule exact to degree 2N, face rule to
+ * degree 2N+1; Section 3.1 for DG-SBP: positive weights, volume rule exact to degree 2N-1
+ * with the face nodes among its nodes).  Caller-owned, copied during init. */
+typedef struct {
+  int32_t vol_degree;     /* 0 = 2N (2N-1 for DG-SBP).  Stroud rule: the collapsed rule with
+                             q = ceil((vol_degree + 1) / 2) points per direction, q = N+1 or
+                             N+2 (vol_degree <= 2N+3).  Caller's rule: the degree it must be
+                             exact to (>= 2N; >= 2N-1 for DG-SBP), checked at init          */
+  int32_t face_points;    /* Gauss-Legendre points per face: 0 = N+1; N+1 or N+2 (DG-SBP: N+1) */
+  int32_t nq;             /* 0 = Stroud rule; else the caller's volume rule of nq nodes:      */
+  const double *rq, *sq;  /*   nodes on the reference triangle (closed)                       */
+  const double *wq;       /*   positive weights (they sum to 2, the reference area)          */
+} esdg_swe_quadrature;
+
+/* The kernels are compiled for volume rules of (N+1)^2 nodes with N+1 face points, and of
+ * (N+2)^2 nodes with N+2 face points; a rule with fewer nodes is padded with zero-weight
+ * nodes (which leave every weighted operator unchanged), so a caller's rule may have up to
+ * (N+2)^2 nodes, and more than (N+1)^2 only with face_points = N+2.  DG-SBP is compiled for
+ * N = 1..4 with rules of exactly 6, 10, 18, 22 nodes. */
+
 /* One independent shallow-water instance on a periodic box, or a domain closed (in one or
  * both directions) by reflective walls. */
 typedef struct {
@@ -140,18 +172,33 @@ typedef struct {
                                one tile, else 0.  With 1 (or 2 resolving to 1) bind fails with
                                ESDG_EDEVICE where cooperative launch is missing.  Results are
                                bitwise the same in every mode.                                */
-  int32_t mass_inverse;     /* ESDG_MASS_STORED | ESDG_MASS_WEIGHT_ADJUSTED                   */
+  int32_t mass_inverse;     /* ESDG_MASS_STORED | ESDG_MASS_WEIGHT_ADJUSTED (modal scheme)     */
+  int32_t tile_shape[6];    /* residual-phase tile shape per degree N = index (1..5), packed
+                               (R << 4) | P: R rows per thread (1, or 2 in FP32 where 2 divides
+                               Nq and Nfq), P column parts (1..4) whose partial sums the lift
+                               adds; 0 = the library's default ((2 << 4) | 2 in FP32 at N = 1
+                               and 3, else (1 << 4) | 2); another shape returns ESDG_EINVAL.
+                               A shape other than the default needs matrix_cores 0 or 1 and
+                               the (N+1)-point quadrature.  The shape changes the summation
+                               order only.                                                   */
+  int32_t scheme;           /* ESDG_SCHEME_MODAL | ESDG_SCHEME_SBP (every instance a caller's
+                               DG-SBP rule; precision FP64 or FP32, flux EC or LF, walls
+                               allowed; contractions, mass_inverse and fused_steps do not apply) */
 } esdg_swe_options;
 
 /* Plan a solver for n_inst independent instances (n_inst = 1 for a single run).  Builds,
- * on the host in double precision, the reference operators of each degree, the
- * isoparametric geometry, the face connectivity (periodic, or reflective walls) and the
+ * on the host in double precision, the reference operators of each degree and quadrature,
+ * the isoparametric geometry, the face connectivity (periodic, or reflective walls) and the
  * inverse curved mass matrices, or with ESDG_MASS_WEIGHT_ADJUSTED the weights w/J
- * (Sections 2.1-2.7, 2.9).  Validates: 1 <= N <= 5, J > 0 at every quadrature node, every
- * face node matched (or on a wall).  On success *out is a new handle and *workspace_bytes the
- * device workspace size esdg_swe_bind needs.  No device call is made. */
-esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const esdg_swe_options *opt,
-                          esdg_swe **out, size_t *workspace_bytes);
+ * (Sections 2.1-2.7, 2.9; Section 3 for DG-SBP).  quad is NULL (every instance the default
+ * rules) or an array of n_inst entries; instances of one degree must use the same
+ * quadrature.  Validates: 1 <= N <= 5 (1..4 for DG-SBP), the quadrature (a caller's rule:
+ * positive weights, nodes in the triangle, exactness to the required degree, for DG-SBP the
+ * face nodes among its nodes; ESDG_EINVAL otherwise), J > 0 at every quadrature node, every
+ * face node matched (or on a wall).  On success *out is a new handle and *workspace_bytes
+ * the device workspace size esdg_swe_bind needs.  No device call is made. */
+esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const esdg_swe_quadrature *quad,
+                          const esdg_swe_options *opt, esdg_swe **out, size_t *workspace_bytes);
 
 /* Attach a caller-owned device workspace (>= workspace_bytes, 256-byte aligned) and a
  * HIP stream (hipStream_t as void*, NULL = default stream), then upload the operators
@@ -159,14 +206,17 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
 esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *hip_stream);
 
 /* Set instance `inst`'s state from samples at its geometry nodes: u_nodes is host
- * [3][K][Np] (h, hu, hv).  The library interpolates to modal coefficients, resets the RK
- * register to zero and computes the entropy projection of the new state.  Synchronous. */
+ * [3][K][(N+1)(N+2)/2] (h, hu, hv).  The library interpolates to modal coefficients (DG-SBP:
+ * evaluates that interpolant at the volume nodes), resets the RK register to zero, sets the
+ * reference level and computes the entropy projection (DG-SBP: the face values) of the new
+ * state.  Synchronous. */
 esdg_status esdg_swe_set_state(esdg_swe *s, int32_t inst, const double *u_nodes);
 
-/* As esdg_swe_set_state, from modal coefficients uh (host [3][K][Np]). */
+/* As esdg_swe_set_state, from the state's own coefficients (host [3][K][Np] of h, hu, hv):
+ * modal coefficients, or for DG-SBP the values at the rule's volume nodes. */
 esdg_status esdg_swe_set_state_modal(esdg_swe *s, int32_t inst, const double *uh);
 
-/* Copy instance `inst`'s modal state to the host as double [3][K][Np].  Synchronises the
+/* Copy instance `inst`'s state (modal, or nodal for DG-SBP) to the host as double [3][K][Np].  Synchronises the
  * stream; returns ESDG_ENONPHYS if any kernel since the last check flagged a bad state. */
 esdg_status esdg_swe_get_state(esdg_swe *s, int32_t inst, double *uh);
 
@@ -223,7 +273,8 @@ esdg_status esdg_swe_sync(esdg_swe *s);
  * the first set_state. */
 esdg_status esdg_swe_reference_level(const esdg_swe *s, int32_t inst, double *Href);
 
-/* Sizes of instance `inst`: out = {N, K, Np, Nq, Nfq, Nh}. */
+/* Sizes of instance `inst`: out = {N, K, Np, Nq, Nfq, Nh} (Np the state values per field and
+ * element; Nq the volume nodes the kernels use, a caller's rule counted with its padding). */
 esdg_status esdg_swe_query(const esdg_swe *s, int32_t inst, int32_t *out6);
 
 /* Launch plan (after bind): out = {element tiles, resident workgroups of the stage kernel,

@@ -37,25 +37,61 @@ class esdg_swe_instance(C.Structure):
 class esdg_swe_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("flux", C.c_int32), ("g", C.c_double),
                 ("use_graph", C.c_int32), ("elems_per_block", C.c_int32 * 6), ("matrix_cores", C.c_int32),
-                ("fused_steps", C.c_int32), ("mass_inverse", C.c_int32)]
+                ("fused_steps", C.c_int32), ("mass_inverse", C.c_int32), ("tile_shape", C.c_int32 * 6),
+                ("scheme", C.c_int32)]
+
+
+class esdg_swe_quadrature(C.Structure):
+    _fields_ = [("vol_degree", C.c_int32), ("face_points", C.c_int32), ("nq", C.c_int32),
+                ("rq", C.POINTER(C.c_double)), ("sq", C.POINTER(C.c_double)), ("wq", C.POINTER(C.c_double))]
 
 
 FUSED = {False: 0, True: 1, "auto": 2}
 MASS = {"stored": 0, "wadg": 1}      # inverse curved mass matrices: stored, or weight-adjusted
+SCHEMES = {"modal": 0, "sbp": 1}     # modal ESDG (hybridized operators), or DG-SBP
+
+
+def _per_degree(v):
+    arr = (C.c_int32 * 6)()
+    if isinstance(v, int):
+        for N in range(1, 6):
+            arr[N] = v
+    elif v:
+        for N, E in v.items():
+            arr[int(N)] = int(E)
+    return arr
+
+
+def shape_code(rows: int, parts: int) -> int:
+    """Tile shape of the residual phase as the ABI packs it: (rows << 4) | parts."""
+    return (int(rows) << 4) | int(parts)
 
 
 def make_options(precision: str, flux: str, g: float, use_graph: bool = True, epb=None,
-                 matrix_cores: bool = False, fused="auto", mass: str = "stored") -> esdg_swe_options:
-    """epb: None, an int (all degrees) or a mapping N -> elements per workgroup."""
-    arr = (C.c_int32 * 6)()
-    if isinstance(epb, int):
-        for N in range(1, 6):
-            arr[N] = epb
-    elif epb:
-        for N, E in epb.items():
-            arr[int(N)] = int(E)
-    return esdg_swe_options(PRECISIONS[precision], FLUXES[flux], float(g), int(use_graph), arr,
-                            2 if matrix_cores else 1, FUSED[fused], MASS[mass])
+                 matrix_cores: bool = False, fused="auto", mass: str = "stored",
+                 scheme: str = "modal", shape=None) -> esdg_swe_options:
+    """epb: None, an int (all degrees) or a mapping N -> elements per workgroup; shape: None,
+    a packed tile shape (all degrees) or a mapping N -> packed shape (shape_code)."""
+    return esdg_swe_options(PRECISIONS[precision], FLUXES[flux], float(g), int(use_graph), _per_degree(epb),
+                            2 if matrix_cores else 1, FUSED[fused], MASS[mass], _per_degree(shape), SCHEMES[scheme])
+
+
+def make_quadrature(spec, keep: list) -> esdg_swe_quadrature:
+    """spec: None (default rules) or a mapping with optional keys vol_degree, face_points and
+    rule = (r, s, w) (a caller's volume rule).  Arrays are appended to ``keep``, which must
+    outlive the init call."""
+    q = esdg_swe_quadrature()
+    if not spec:
+        return q
+    q.vol_degree = int(spec.get("vol_degree", 0))
+    q.face_points = int(spec.get("face_points", 0))
+    rule = spec.get("rule")
+    if rule is not None:
+        r, s_, w = (np.ascontiguousarray(a, dtype=np.float64) for a in rule)
+        keep += [r, s_, w]
+        q.nq = int(w.size)
+        q.rq, q.sq, q.wq = _dptr(r), _dptr(s_), _dptr(w)
+    return q
 
 
 class EsdgError(RuntimeError):
@@ -81,8 +117,8 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
     lib = C.CDLL(p)
     vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
     pdbl = C.POINTER(C.c_double)
-    lib.esdg_swe_init.argtypes = [i32, C.POINTER(esdg_swe_instance), C.POINTER(esdg_swe_options), C.POINTER(vp),
-                                  C.POINTER(C.c_size_t)]
+    lib.esdg_swe_init.argtypes = [i32, C.POINTER(esdg_swe_instance), C.POINTER(esdg_swe_quadrature),
+                                  C.POINTER(esdg_swe_options), C.POINTER(vp), C.POINTER(C.c_size_t)]
     lib.esdg_swe_bind.argtypes = [vp, vp, C.c_size_t, vp]
     lib.esdg_swe_set_state.argtypes = [vp, i32, pdbl]
     lib.esdg_swe_set_state_modal.argtypes = [vp, i32, pdbl]
@@ -118,7 +154,9 @@ class EsdgSwe:
     def __init__(self, instances: Sequence, precision: str = "fp64", flux: str = "lf", g: float = 1.0,
                  elems_per_block=None, use_graph: bool = True, device: str = "cuda:0", stream=None,
                  tuned: bool = True, matrix_cores: Optional[bool] = None, fused: Optional[bool] = None,
-                 mass: str = "stored"):
+                 mass: str = "stored", quadrature=None, scheme: str = "modal", tile_shape=None):
+        """quadrature: None, one spec for every instance, or a list of specs (make_quadrature);
+        scheme: "modal" (Section 2) or "sbp" (DG-SBP of Section 3, each spec with its rule)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("EsdgSwe needs a GPU: the library has no CPU path")
@@ -133,19 +171,29 @@ class EsdgSwe:
             b = np.ascontiguousarray(w.b_nodes, dtype=np.float64)
             self._keep += [xg, yg, b]
             arr[i] = esdg_swe_instance(w.N, w.K, _dptr(xg), _dptr(yg), _dptr(b), w.Lx, w.Ly)
-        if not elems_per_block and tuned:
-            from .autotune import lookup
-            elems_per_block = lookup(precision, [(w.N, w.K) for w in instances])
+        if quadrature is None or isinstance(quadrature, dict):
+            quadrature = [quadrature] * len(instances)
+        qarr = (esdg_swe_quadrature * len(instances))()
+        for i, spec in enumerate(quadrature):
+            qarr[i] = make_quadrature(spec, self._keep)
+        default_rules = scheme == "modal" and not any(quadrature)
+        if not elems_per_block and tuned and default_rules:   # the tuning cache covers the default rules
+            from .autotune import lookup_shapes
+            elems_per_block, tuned_shape = lookup_shapes(precision, [(w.N, w.K) for w in instances])
+            if tile_shape is None:
+                tile_shape = tuned_shape
         if matrix_cores is None:
             matrix_cores = os.environ.get("ESDG_SWE_MATRIX_CORES", "0") == "1"
         if fused is None:       # one launch per step call when tiles can stay resident
             fused = {"0": False, "1": True}.get(os.environ.get("ESDG_SWE_FUSED", ""), "auto")
         self.elems_per_block = elems_per_block
-        opt = make_options(precision, flux, g, use_graph, elems_per_block, matrix_cores, fused, mass)
+        self.tile_shape = tile_shape
+        opt = make_options(precision, flux, g, use_graph, elems_per_block, matrix_cores, fused, mass, scheme, tile_shape)
         self.mass = mass
+        self.scheme = scheme
         h = C.c_void_p()
         nbytes = C.c_size_t()
-        st = self.lib.esdg_swe_init(len(instances), arr, C.byref(opt), C.byref(h), C.byref(nbytes))
+        st = self.lib.esdg_swe_init(len(instances), arr, qarr, C.byref(opt), C.byref(h), C.byref(nbytes))
         if st != ESDG_OK:
             raise EsdgError(st, self.lib.esdg_swe_last_error(None).decode())
         self.h = h
@@ -176,9 +224,10 @@ class EsdgSwe:
 
     # -- C-ABI entry points (same names) ------------------------------------------
     def esdg_swe_set_state(self, inst: int, u_nodes: np.ndarray):
+        """u_nodes: (h, hu, hv) at the geometry nodes, [3][K][(N+1)(N+2)/2]."""
         u = np.ascontiguousarray(u_nodes, dtype=np.float64)
         z = self.sizes[inst]
-        assert u.shape == (3, z["K"], z["Np"]), u.shape
+        assert u.shape == (3, z["K"], (z["N"] + 1) * (z["N"] + 2) // 2), u.shape
         self._check(self.lib.esdg_swe_set_state(self.h, inst, _dptr(u)))
 
     def esdg_swe_set_state_modal(self, inst: int, uh: np.ndarray):

@@ -14,7 +14,14 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIBDIR = os.path.join(HERE, "_lib")
 LIBNAME = "libesdg_swe.so"
-SOURCES = ["host_setup.cpp", "kernels.hip", "runtime.cpp", "volume_bench.hip"]
+# (source, extra defines): kernels.hip is compiled once per (precision, mass inverse) for its
+# stage kernels and once for the rest, so that the objects build in parallel
+SOURCES = [("host_setup.cpp", []), ("runtime.cpp", []), ("volume_bench.hip", []),
+           ("kernels.hip", ["-DESDG_UNIT_HOST"]),
+           ("kernels.hip", ["-DESDG_UNIT_REAL=float", "-DESDG_UNIT_WADG=0"]),
+           ("kernels.hip", ["-DESDG_UNIT_REAL=float", "-DESDG_UNIT_WADG=1"]),
+           ("kernels.hip", ["-DESDG_UNIT_REAL=double", "-DESDG_UNIT_WADG=0"]),
+           ("kernels.hip", ["-DESDG_UNIT_REAL=double", "-DESDG_UNIT_WADG=1"])]
 
 HIPFLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -28,18 +35,31 @@ def library_path() -> str:
     return os.path.join(LIBDIR, LIBNAME)
 
 
-def build_library(verbose: bool = False) -> str:
+def build_library(verbose: bool = False, jobs: int = 0) -> str:
+    from concurrent.futures import ThreadPoolExecutor
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     os.makedirs(LIBDIR, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(LIBDIR, os.path.splitext(src)[0] + ".o")
+    cmds, objs = [], []
+    for i, (src, defs) in enumerate(SOURCES):
+        obj = os.path.join(LIBDIR, f"{os.path.splitext(src)[0]}_{i}.o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [hipcc, *HIPFLAGS, "-I" + INCLUDE, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmds.append([hipcc, *HIPFLAGS, *defs, "-I" + INCLUDE, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    jobs = jobs or min(len(cmds), max(1, min(16, os.cpu_count() or 1)))
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+        return subprocess.run(cmd, capture_output=True, text=True)
+
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(run, cmds))
+    for cmd, r in zip(cmds, results):
+        err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
+        if err.strip():
+            print(err, file=sys.stderr, flush=True)
+        if r.returncode != 0:
+            raise subprocess.CalledProcessError(r.returncode, cmd)
     out = library_path()
     tmp = out + ".tmp"
     cmd = [hipcc, "-shared", "--offload-arch=gfx950", "-fPIC", *objs, "-o", tmp]

@@ -16,50 +16,98 @@ constexpr int kXcds = 8;           // MI355X accelerator complex dies (each with
 // writes the mirror state into its own neighbour slot (the target's other bits).
 constexpr uint32_t kPushWall = 0x80000000u;
 
-__host__ __device__ constexpr int dim_Np(int N) { return (N + 1) * (N + 2) / 2; }
-__host__ __device__ constexpr int dim_Nq(int N) { return (N + 1) * (N + 1); }
-__host__ __device__ constexpr int dim_Nfq(int N) { return 3 * (N + 1); }
-__host__ __device__ constexpr int dim_Nh(int N) { return dim_Nq(N) + dim_Nfq(N); }
+// Element kinds.  A key D = N | (variant << 3) names the degree N and the node sets the
+// kernels are compiled for:
+//   variant 0: volume rule of (N+1)^2 nodes (the Stroud collapsed rule, or a caller's rule of
+//              at most that many nodes padded with zero-weight nodes), N+1 Gauss-Legendre
+//              points per face;
+//   variant 1: (N+2)^2 volume nodes (likewise), N+2 Gauss-Legendre points per face;
+//   variant 2: the DG-SBP scheme of Section 3: a volume rule of sbp_nodes(N) nodes whose
+//              boundary nodes are the N+1 Gauss-Legendre points of every face; the state is
+//              the nodal values at the volume nodes.
+// A plain degree N (variant 0) is its own key.
+constexpr int kKeyShift = 3;
+constexpr int kMaxKey = (2 << kKeyShift) | kMaxN;
+__host__ __device__ constexpr int key_N(int D) { return D & ((1 << kKeyShift) - 1); }
+__host__ __device__ constexpr int key_variant(int D) { return D >> kKeyShift; }
+__host__ __device__ constexpr int make_key(int N, int variant) { return N | (variant << kKeyShift); }
+__host__ __device__ constexpr bool key_sbp(int D) { return key_variant(D) == 2; }
+// Nodes of the DG-SBP volume rules the kernels are compiled for (N = 1..4).
+__host__ __device__ constexpr int sbp_nodes(int N) { return N == 1 ? 6 : N == 2 ? 10 : N == 3 ? 18 : N == 4 ? 22 : 0; }
 
-// Relative cost of one element of degree N in a stage (flux-differencing and contraction
+__host__ __device__ constexpr int dim_modes(int D) { return (key_N(D) + 1) * (key_N(D) + 2) / 2; }
+__host__ __device__ constexpr int dim_Nfp(int D) { return key_N(D) + 1 + (key_variant(D) == 1); }
+__host__ __device__ constexpr int dim_Nq(int D) {
+  return key_sbp(D) ? sbp_nodes(key_N(D)) : (key_N(D) + 1 + key_variant(D)) * (key_N(D) + 1 + key_variant(D));
+}
+// values per field and element of the state: modal coefficients, or nodal values (DG-SBP)
+__host__ __device__ constexpr int dim_Np(int D) { return key_sbp(D) ? dim_Nq(D) : dim_modes(D); }
+__host__ __device__ constexpr int dim_Nfq(int D) { return 3 * dim_Nfp(D); }
+__host__ __device__ constexpr int dim_Nh(int D) { return dim_Nq(D) + dim_Nfq(D); }
+
+// Relative cost of one element of kind D in a stage (flux-differencing and contraction
 // flops), used to balance persistent workgroups over mixed-degree tile lists.
-__host__ __device__ constexpr long long elem_cost(int N) {
-  return 35LL * (dim_Nq(N) * (dim_Nq(N) - 1) / 2 + dim_Nq(N) * dim_Nfq(N)) +
-         6LL * (2 * dim_Nq(N) * dim_Np(N) + 2 * dim_Np(N) * dim_Np(N) + 2 * dim_Nh(N) * dim_Np(N));
+__host__ __device__ constexpr long long elem_cost(int D) {
+  return 35LL * (dim_Nq(D) * (dim_Nq(D) - 1) / 2 + dim_Nq(D) * dim_Nfq(D)) +
+         (key_sbp(D) ? 0LL
+                     : 6LL * (2 * dim_Nq(D) * dim_Np(D) + 2 * dim_Np(D) * dim_Np(D) + 2 * dim_Nh(D) * dim_Np(D)));
 }
 
-// Reference-operator block of degree N, stored contiguously in the bulk precision:
-//   Vh [Nh][Np]
+// Reference-operator block of kind D, stored contiguously in the bulk precision:
+//   Vh [Nh][Np]     (modal kinds only)
 //   ST [Nh][Nq][2]  ST[n][m] = (S^r[m][n], S^s[m][n]) for volume rows m (column-major
 //                   so one column's entries for consecutive rows are contiguous)
 //   FT [Nq][Nfq][2] FT[n][f] = (-S^r[n][Nq+f], -S^s[n][Nq+f]): face row f, volume column n
 //   wf [Nfq] | nr [Nfq] | ns [Nfq]
+//   DG-SBP only: fvol [Nfq] (int32: the volume node at face node f) | vface [Nq] (int32:
+//   the face node at volume node n, or -1)
 // where S^j = 1/2 (Qhat_h^j - Qhat_h^j^T) (its surface-surface block is zero).
-__host__ __device__ constexpr int ref_words(int N) {
-  return dim_Nh(N) * dim_Np(N) + 2 * dim_Nh(N) * dim_Nq(N) + 2 * dim_Nq(N) * dim_Nfq(N) + 3 * dim_Nfq(N);
+__host__ __device__ constexpr int ref_words(int D) {
+  return (key_sbp(D) ? dim_Nfq(D) + dim_Nq(D) : dim_Nh(D) * dim_Np(D)) + 2 * dim_Nh(D) * dim_Nq(D) +
+         2 * dim_Nq(D) * dim_Nfq(D) + 3 * dim_Nfq(D);
 }
 
 // Reals per element of the mass-matrix data: the stored inverse (M_h^k)^{-1} [Np][Np], or,
-// with the weight-adjusted inverse, the quadrature weights over J at the volume nodes [Nq].
-__host__ __device__ constexpr int mass_words(int N, bool wadg) {
-  return wadg ? dim_Nq(N) : dim_Np(N) * dim_Np(N);
+// with the weight-adjusted inverse, the quadrature weights over J at the volume nodes [Nq]
+// (DG-SBP: the inverse of the diagonal mass matrix, 1/(w J) [Nq]).
+__host__ __device__ constexpr int mass_words(int D, bool wadg) {
+  return (wadg || key_sbp(D)) ? dim_Nq(D) : dim_Np(D) * dim_Np(D);
 }
 
-// Words (of the bulk precision) of LDS one tile of E elements of degree N needs (the
-// reference block is held separately, once per workgroup): node records [E][Nh][kNodeRec] | fetched u~ and metrics [8][E][Nh] |
-// neighbour values [E][Nfq][4] | state, RK register [3][E][Np] each | mass data
-// [E][mass_words] | w J [E][Nq] | b at volume nodes [E][Nq] | b at hybrid nodes [E][Nh] |
-// push targets [E][Nfq] (int32, one word of the bulk precision each).
-__host__ __device__ constexpr int tile_words(int N, int E, bool wadg = false) {
-  return E * (dim_Nh(N) * kNodeRec + 8 * dim_Nh(N) + 4 * dim_Nfq(N) + 6 * dim_Np(N) +
-                             mass_words(N, wadg) + 2 * dim_Nq(N) + dim_Nh(N) + dim_Nfq(N));
+// Reals per element of the static per-tile block (see InstDesc::stat).  Modal kinds: the
+// mass data, w J, the rest depth Href - b at the volume and at the hybrid nodes, and the
+// face push targets (int32, one real-sized slot each).  DG-SBP: 1/(w J), the rest depth and
+// the metric factors rxJ, sxJ, ryJ, syJ at the volume nodes, and the push targets.
+__host__ __device__ constexpr int stat_words(int D, bool wadg = false) {
+  return key_sbp(D) ? 6 * dim_Nq(D) + dim_Nfq(D)
+                    : mass_words(D, wadg) + 2 * dim_Nq(D) + dim_Nh(D) + dim_Nfq(D);
 }
 
-// Reals per element of the static per-tile block (see InstDesc::stat): the mass data, w J,
-// b at the volume and at the hybrid nodes, and the face push targets (int32, one real-sized
-// slot each).
-__host__ __device__ constexpr int stat_words(int N, bool wadg = false) {
-  return mass_words(N, wadg) + 2 * dim_Nq(N) + dim_Nh(N) + dim_Nfq(N);
+// Tile shape of the residual phase: rows per thread R (it divides Nq and Nfq) and column
+// parts P, packed as (R << 4) | P.  A task is (element, R rows, column part); the P partial
+// sums of a row are added in the lift.
+constexpr int kShapeDefault = 0;
+__host__ __device__ constexpr int shape_rows(int shape) { return shape >> 4; }
+__host__ __device__ constexpr int shape_parts(int shape) { return shape & 15; }
+__host__ __device__ constexpr int make_shape(int R, int P) { return (R << 4) | P; }
+
+// Reals per element of the block that holds the fetched u~ and metric factors [8][Nh]
+// (dead after the node records) and then the P residual partials [P][3][Nh] and the lift's
+// output [3][Np].
+__host__ __device__ constexpr int raw_words(int D, int P) {
+  return 8 * dim_Nh(D) > 3 * P * dim_Nh(D) + 3 * dim_Np(D) ? 8 * dim_Nh(D) : 3 * P * dim_Nh(D) + 3 * dim_Np(D);
+}
+
+// Words (of the bulk precision) of LDS one tile of E elements of kind D needs (the
+// reference block is held separately, once per workgroup).  Modal kinds: node records
+// [E][Nh][kNodeRec] | raw block [E][raw_words] | neighbour values [E][Nfq][4] | state, RK
+// register [3][E][Np] each | static block [E][stat_words].  DG-SBP: node records | two
+// residual partials [2][3][E][Nh] | neighbour values | state, RK register [3][E][Nq] each |
+// static block.
+__host__ __device__ constexpr int tile_words(int D, int E, bool wadg = false, int P = 2) {
+  return key_sbp(D) ? E * (dim_Nh(D) * kNodeRec + 6 * dim_Nh(D) + 4 * dim_Nfq(D) + 6 * dim_Nq(D) + stat_words(D))
+                    : E * (dim_Nh(D) * kNodeRec + raw_words(D, P) + 4 * dim_Nfq(D) + 6 * dim_Np(D) +
+                           stat_words(D, wadg));
 }
 
 // 32-bit words per thread of the static block that a stage stages through registers
@@ -70,7 +118,8 @@ template <typename real> struct StatRegs { static constexpr int value = sizeof(r
 
 // One instance as the kernels see it (device pointers into the bound workspace).
 struct InstDesc {
-  int32_t N, K, flux, pad0;
+  int32_t N, K, flux;   // N: the element kind D (degree | variant << kKeyShift)
+  int32_t shape;        // tile shape of the residual phase, (R << 4) | P
   double g, Href, dt, pad1;
   void *uh;            // [3][K][Np] modal state (eta = h + b - Href, hu, hv)
   void *du;            // [3][K][Np] LSRK register
@@ -80,16 +129,22 @@ struct InstDesc {
   void *nbx[3];        // [K][Nfq][4] the same four values at each face node's neighbour, written
                        // by the neighbour's projection (one per ut buffer)
   const void *geo;     // rxJ, sxJ, ryJ, syJ at the hybrid nodes, tile-blocked like ut
-  const void *wJq;     // [K][Nq] w_q J (diagnostics)
-  const void *bq;      // [K][Nq] bathymetry at volume nodes (diagnostics)
+  const void *wJq;     // [K][Nq] w_q J in double (diagnostics)
   const void *stat;    // static data in tile order: the tile of elements k0..k0+ne-1 holds, from
                        // real k0 * stat_words(N, wadg): the mass data [ne][mass_words] (Minv
-                       // [Np][Np], or w/J at the volume nodes [Nq]) | w J [ne][Nq] | b [ne][Nq] |
-                       // b [ne][Nh] | push targets [ne][Nfq] (int32 k'*Nfq + f' of the nbx slot
-                       // that face node f fills, packed in the first ne*Nfq 32-bit words;
-                       // kPushWall set on wall nodes, whose slot is their own)
-  const void *ref;     // reference-operator block for this N
+                       // [Np][Np], or w/J at the volume nodes [Nq]) | w J [ne][Nq] | rest depth
+                       // Href - b [ne][Nq] | Href - b [ne][Nh] | push targets [ne][Nfq] (int32
+                       // k'*Nfq + f' of the nbx slot that face node f fills, packed in the first
+                       // ne*Nfq 32-bit words; kPushWall set on wall nodes, whose slot is their
+                       // own).  DG-SBP: 1/(w J) [ne][Nq] | Href - b [ne][Nq] | rxJ, sxJ, ryJ, syJ
+                       // [4][ne][Nq] | push targets [ne][Nfq].  The rest depth is rewritten from
+                       // bd (double) whenever Href changes, so a near-dry depth h = eta +
+                       // (Href - b) keeps its relative accuracy in float.
+  const void *ref;     // reference-operator block for this kind
   void *rhs_scratch;   // [3][K][Np] used by the diagnostics
+  const double *bd;    // [K][Nh] bathymetry at the hybrid nodes in double (volume nodes first):
+                       // the source of the rest depth Href - b written into the static block
+  const double *Vqd;   // V_q [Nq][Np] in double (diagnostics; modal kinds)
 };
 
 // A contiguous range of elements of one instance, processed by one workgroup.
@@ -112,7 +167,9 @@ struct StageArgs {
   int32_t contraction;    // constant-matrix contractions: 0 VALU, 1 matrix cores in the bulk
                           // precision, 2 matrix cores with split-bf16 products
   int32_t wadg;           // 0: stored inverse mass matrices; 1: weight-adjusted inverse
-  int32_t pad_w;
+  int32_t v1;             // an instance is of a variant-1 kind (selects the stage-kernel build)
+  int32_t shapes;         // an instance's tile shape is not the default (selects the build)
+  int32_t pad_s;
   const int32_t *ranges;  // optional [grid+1]: tile range of each block's chunk (cost-balanced);
                           // null means equal numbers of tiles per chunk
   int32_t in_buf, out_buf;
@@ -141,7 +198,7 @@ struct DiagArgs {
   const InstDesc *desc;
   const Tile *tiles;
   int32_t ntiles;
-  int32_t pad;
+  int32_t wadg;           // static-block layout of the modal kinds (weight-adjusted inverse)
   double *partials;       // [ntiles][6]
 };
 

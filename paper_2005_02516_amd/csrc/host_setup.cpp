@@ -1,6 +1,7 @@
 // Host-side FP64 setup: reference element, isoparametric geometry, face connectivity
 // (periodic, or reflective walls) and inverse curved mass matrices.  See host_setup.hpp.
 #include "host_setup.hpp"
+#include "device_types.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -182,36 +183,118 @@ bool spd_inverse(int n, const double *A, double *Ainv) {
 
 }  // namespace
 
-RefElem build_ref(int N) {
+std::string check_rule(const QuadRule &q, int degree) {
+  const size_t n = q.w.size();
+  if (n == 0 || q.r.size() != n || q.s.size() != n) return "quadrature rule: empty, or r, s, w of different lengths";
+  char buf[200];
+  for (size_t i = 0; i < n; ++i) {
+    if (!(q.w[i] > 0.0) || !std::isfinite(q.w[i])) {
+      std::snprintf(buf, sizeof buf, "quadrature rule: weight %zu is %.3e (must be positive)", i, q.w[i]);
+      return buf;
+    }
+    const double r = q.r[i], s = q.s[i];
+    if (!(r >= -1.0 - 1e-12 && s >= -1.0 - 1e-12 && r + s <= 1e-12)) {
+      std::snprintf(buf, sizeof buf, "quadrature rule: node %zu (%.6f, %.6f) outside the reference triangle", i, r, s);
+      return buf;
+    }
+  }
+  // int_T r^a s^b = int_{-1}^{1} s^b ((-s)^(a+1) - (-1)^(a+1)) / (a+1) ds
+  auto pint = [](int p) { return (p % 2) ? 0.0 : 2.0 / (p + 1); };
+  for (int d = 0; d <= degree; ++d)
+    for (int a = 0; a <= d; ++a) {
+      const int b = d - a;
+      const double sg = (a + 1) % 2 ? -1.0 : 1.0;   // (-1)^(a+1)
+      const double exact = sg * (pint(a + b + 1) - pint(b)) / (a + 1);
+      double sum = 0.0, mag = 0.0;
+      for (size_t i = 0; i < n; ++i) {
+        const double t = q.w[i] * std::pow(q.r[i], a) * std::pow(q.s[i], b);
+        sum += t;
+        mag += std::fabs(t);
+      }
+      if (std::fabs(sum - exact) > 1e-12 * std::max(1.0, mag)) {
+        std::snprintf(buf, sizeof buf, "quadrature rule: not exact for r^%d s^%d (degree %d required): %.6e vs %.6e",
+                      a, b, degree, sum, exact);
+        return buf;
+      }
+    }
+  return "";
+}
+
+RefElem build_ref(int N, int variant, const QuadRule *rule, std::string *err) {
   RefElem R;
+  const int D = make_key(N, variant);
   R.N = N;
+  R.key = D;
   R.Np = n_modes(N);
-  R.Nfp = N + 1;
-  R.Nq = (N + 1) * (N + 1);
-  R.Nfq = 3 * (N + 1);
+  R.Nfp = dim_Nfp(D);
+  R.Nq = dim_Nq(D);
+  R.Nfq = dim_Nfq(D);
   R.Nh = R.Nq + R.Nfq;
   const int Np = R.Np, Nq = R.Nq, Nfq = R.Nfq, Nh = R.Nh, Nfp = R.Nfp;
-  // volume rule: Gauss-Legendre in a times Gauss-Jacobi(1,0) in b, collapsed
-  std::vector<double> xa, wa, xb, wb;
-  gauss_jacobi(N + 1, 0.0, 0.0, xa, wa);
-  gauss_jacobi(N + 1, 1.0, 0.0, xb, wb);
-  for (int i = 0; i <= N; ++i)
-    for (int j = 0; j <= N; ++j) {
-      R.rq.push_back((1.0 + xa[i]) * (1.0 - xb[j]) / 2.0 - 1.0);
-      R.sq.push_back(xb[j]);
-      R.wq.push_back(0.5 * wa[i] * wb[j]);
-    }
-  // faces: s=-1 (v1->v2), r+s=0 (v2->v3), r=-1 (v3->v1)
+  // volume rule: the caller's, or Gauss-Legendre in a times Gauss-Jacobi(1,0) in b, collapsed
+  if (rule) {
+    R.rq = rule->r; R.sq = rule->s; R.wq = rule->w;
+  } else {
+    std::vector<double> xa, wa, xb, wb;
+    const int q = N + 1 + variant;
+    gauss_jacobi(q, 0.0, 0.0, xa, wa);
+    gauss_jacobi(q, 1.0, 0.0, xb, wb);
+    for (int i = 0; i < q; ++i)
+      for (int j = 0; j < q; ++j) {
+        R.rq.push_back((1.0 + xa[i]) * (1.0 - xb[j]) / 2.0 - 1.0);
+        R.sq.push_back(xb[j]);
+        R.wq.push_back(0.5 * wa[i] * wb[j]);
+      }
+  }
+  R.nrule = int(R.wq.size());
+  if (R.nrule > Nq || (variant == 2 && R.nrule != Nq)) {
+    if (err) *err = "quadrature rule has " + std::to_string(R.nrule) + " nodes; this element kind takes " +
+                    (variant == 2 ? "exactly " : "at most ") + std::to_string(Nq);
+    return R;
+  }
+  // zero-weight padding (at the centroid): such a node has zero rows and columns in every
+  // weighted operator, so it leaves the scheme unchanged
+  while (int(R.wq.size()) < Nq) {
+    R.rq.push_back(-1.0 / 3.0);
+    R.sq.push_back(-1.0 / 3.0);
+    R.wq.push_back(0.0);
+  }
+  // faces: s=-1 (v1->v2), r+s=0 (v2->v3), r=-1 (v3->v1), Nfp Gauss-Legendre points each
+  std::vector<double> xf, wfl;
+  gauss_jacobi(Nfp, 0.0, 0.0, xf, wfl);
   for (int f = 0; f < 3; ++f)
     for (int i = 0; i < Nfp; ++i) {
-      const double t = xa[i];
+      const double t = xf[i];
       double r, s, nr_, ns_;
       if (f == 0) { r = t; s = -1.0; nr_ = 0.0; ns_ = -1.0; }
       else if (f == 1) { r = -t; s = t; nr_ = 1.0; ns_ = 1.0; }
       else { r = -1.0; s = -t; nr_ = -1.0; ns_ = 0.0; }
-      R.rf.push_back(r); R.sf.push_back(s); R.wf.push_back(wa[i]);
+      R.rf.push_back(r); R.sf.push_back(s); R.wf.push_back(wfl[i]);
       R.nr.push_back(nr_); R.ns.push_back(ns_);
     }
+  if (variant == 2) {              // DG-SBP: every face node is one of the volume nodes
+    R.fvol.assign(Nfq, -1);
+    R.vface.assign(Nq, -1);
+    for (int f = 0; f < Nfq; ++f) {
+      for (int q = 0; q < Nq; ++q)
+        if (std::hypot(R.rq[q] - R.rf[f], R.sq[q] - R.sf[f]) < 1e-12) {
+          R.fvol[f] = q;
+          break;
+        }
+      if (R.fvol[f] < 0) {
+        char buf[200];
+        std::snprintf(buf, sizeof buf, "DG-SBP rule: face node (%.6f, %.6f) (Gauss-Legendre point %d of face %d) is "
+                      "not a volume node", R.rf[f], R.sf[f], f % Nfp, f / Nfp);
+        if (err) *err = buf;
+        return R;
+      }
+      if (R.vface[R.fvol[f]] >= 0) {
+        if (err) *err = "DG-SBP rule: two face nodes at one volume node";
+        return R;
+      }
+      R.vface[R.fvol[f]] = f;
+    }
+  }
   // basis at hybrid nodes
   R.Vh = Mat(Nh, Np); R.Vrh = Mat(Nh, Np); R.Vsh = Mat(Nh, Np);
   for (int n = 0; n < Nh; ++n) {
@@ -236,12 +319,17 @@ RefElem build_ref(int N) {
     }
   for (int f = 0; f < Nfq; ++f)
     for (int i = 0; i < Np; ++i) Vf(f, i) = R.Vh(Nq + f, i);
-  // M, Pq = M^-1 Vq^T W
+  // M, Pq = M^-1 Vq^T W (M is the identity for a rule exact to degree 2N; a DG-SBP rule of
+  // degree 2N-1 gives another symmetric positive definite M)
   Mat VqTW = transpose(Vq);
   for (int i = 0; i < Np; ++i)
     for (int q = 0; q < Nq; ++q) VqTW(i, q) *= R.wq[q];
   Mat M = matmul(VqTW, Vq), Minv;
-  invert(M, Minv);
+  if (!invert(M, Minv)) {
+    if (err) *err = "quadrature rule: the mass matrix V_q^T W V_q is singular (too few nodes for degree " +
+                    std::to_string(N) + ")";
+    return R;
+  }
   Mat Pq = matmul(Minv, VqTW);
   Mat E = matmul(Vf, Pq);
   Mat PqT = transpose(Pq);
@@ -258,6 +346,7 @@ RefElem build_ref(int N) {
       for (int f = 0; f < Nfq; ++f) S(m, Nq + f) = 0.5 * E(f, m) * R.wf[f] * nd[f];
     }
   }
+  if (err) err->clear();
   return R;
 }
 
@@ -305,7 +394,7 @@ void nodes_to_modes(const RefElem &R, int K, const double *u, double *uh) {
 std::string build_instance(const RefElem &R, int K, const double *xg, const double *yg, const double *b, double Lx,
                            double Ly, InstanceHost &out, bool want_minv) {
   const int Np = R.Np, Nq = R.Nq, Nh = R.Nh, Nfp = R.Nfp, Nfq = R.Nfq;
-  out.N = R.N; out.K = K; out.Lx = Lx; out.Ly = Ly;
+  out.N = R.N; out.key = R.key; out.K = K; out.Lx = Lx; out.Ly = Ly;
   out.geo.assign(size_t(4) * K * Nh, 0.0);
   out.wJq.assign(size_t(K) * Nq, 0.0);
   if (want_minv) out.Minv.assign(size_t(K) * Np * Np, 0.0);

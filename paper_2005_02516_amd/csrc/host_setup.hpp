@@ -23,11 +23,25 @@ struct Mat {
   double operator()(int i, int j) const { return a[size_t(i) * cols + j]; }
 };
 
-// Reference element of degree N (Sections 2.1-2.3).
+// A volume quadrature rule on the reference triangle given by the caller.
+struct QuadRule {
+  std::vector<double> r, s, w;
+};
+
+// Checks a caller's volume rule: positive weights, nodes in the closed reference triangle,
+// and exactness for every monomial r^a s^b with a + b <= degree (against the closed-form
+// integrals).  Returns "" or an error message.
+std::string check_rule(const QuadRule &q, int degree);
+
+// Reference element of one element kind (Sections 2.1-2.3; Section 3 for DG-SBP).
 struct RefElem {
   int N = 0, Np = 0, Nq = 0, Nfp = 0, Nfq = 0, Nh = 0;
-  std::vector<double> rq, sq, wq;        // volume rule (Stroud, (N+1)^2 points)
-  std::vector<double> rf, sf, wf;        // face rule, faces 1..3, N+1 Gauss points each
+  int key = 0;                           // element kind (device_types.hpp): N | variant << 3
+  int nrule = 0;                         // nodes of the volume rule before zero-weight padding
+  std::vector<double> rq, sq, wq;        // volume rule (Nq nodes; zero-weight padding at the end)
+  std::vector<double> rf, sf, wf;        // face rule, faces 1..3, Nfp Gauss points each
+  std::vector<int> fvol, vface;          // DG-SBP: volume node of each face node, face node of
+                                         // each volume node (-1 if none)
   std::vector<double> nr, ns;            // reference normals scaled by the face Jacobian
   Mat Vh, Vrh, Vsh;                      // basis and its r/s derivatives at the Nh hybrid nodes
   Mat Vgeo_inv;                          // equispaced node values -> modal coefficients
@@ -36,11 +50,15 @@ struct RefElem {
   Mat Sr, Ss;
 };
 
-RefElem build_ref(int N);
+// Reference element of degree N and variant 0, 1 (modal; Stroud rule with N+1+variant
+// points per direction, or the caller's rule padded with zero-weight nodes to the variant's
+// node count) or 2 (DG-SBP; the caller's rule, whose boundary nodes must include the N+1
+// Gauss-Legendre points of every face).  Returns "" or an error message in *err.
+RefElem build_ref(int N, int variant, const QuadRule *rule, std::string *err);
 
 // Per-instance host data produced from the caller's mesh (Section 2.7).
 struct InstanceHost {
-  int N = 0, K = 0;
+  int N = 0, K = 0, key = 0;
   double Lx = 0, Ly = 0;
   std::vector<double> geo;    // [4][K][Nh]: rxJ, sxJ, ryJ, syJ (J-scaled metric cofactors)
   std::vector<double> wJq;    // [K][Nq]: w_q * J at volume nodes

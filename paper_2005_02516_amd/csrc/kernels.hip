@@ -155,8 +155,8 @@ struct Lds {
   real *R, *T, *Q, *VH;
   int32_t *pp;
   // sm: the ref block (already loaded); tile: the tile region (after the largest ref block);
-  // mw: reals of mass data per element (mass_words)
-  __device__ Lds(real *sm, real *tile, int E, int mw) {
+  // mw: reals of mass data per element (mass_words); P: column parts of the residual
+  __device__ Lds(real *sm, real *tile, int E, int mw, int P) {
     ref = sm;
     Vh = ref;
     ST = Vh + Nh * Np;
@@ -166,7 +166,7 @@ struct Lds {
     ns = nr + Nfq;
     rec = tile;
     raw = rec + E * Nh * kNodeRec;
-    nb = raw + 8 * E * Nh;
+    nb = raw + E * raw_words(N, P);
     U = nb + 4 * E * Nfq;
     DU = U + 3 * E * Np;
     Minv = DU + 3 * E * Np;
@@ -177,22 +177,27 @@ struct Lds {
     // reuse: the residual, lift and projection temporaries live in the raw block (dead
     // after phase 1) and v'_h in the neighbour block (dead after the residual); the
     // node records and the state are left alone, so a resident tile keeps them
-    R = raw;                      // up to two partial residuals [2][3][E][Nh]
-    T = raw + 6 * E * Nh;         // [3][E][Np]
+    R = raw;                      // the P partial residuals [P][3][E][Nh]
+    T = raw + 3 * P * E * Nh;     // [3][E][Np]
     Q = raw;                      // [3][E][Nq] projection's weighted entropy variables
     VH = nb;                      // [3][E][Np] v'_h (3 Np <= 4 Nfq for N <= 5)
   }
 };
 
-// Rows per thread in the residual phase, per degree (must divide Nq and Nfq).  Double tiles
-// take one row per task: two rows of double accumulators exceed the register budget of four
-// waves per SIMD and spill.
+// Default rows per thread of the residual phase (the build without tile-shape choice).
 template <typename real, int N> struct RowsPerThread { static constexpr int value = 1; };
 template <> struct RowsPerThread<float, 1> { static constexpr int value = 2; };
 template <> struct RowsPerThread<float, 3> { static constexpr int value = 2; };
 
-// Column parts of the residual phase, per degree (1 or 2).
-template <int N> struct ColParts { static constexpr int value = 2; };
+// Tile shapes the residual phase is compiled for: R = 1 or 2 rows per thread (2 only in
+// float, where R divides Nq and Nfq: two rows of double accumulators exceed the register
+// budget of four waves per SIMD and spill) and P = 1..4 column parts.
+template <typename real, int N>
+__host__ __device__ constexpr bool shape_ok(int shape) {
+  return shape_parts(shape) >= 1 && shape_parts(shape) <= 4 &&
+         (shape_rows(shape) == 1 ||
+          (shape_rows(shape) == 2 && sizeof(real) == 4 && dim_Nq(N) % 2 == 0 && dim_Nfq(N) % 2 == 0));
+}
 
 // Stage flags of a multi-stage launch whose tiles stay in LDS (StageArgs::resident).
 constexpr int kResident = 1;       // the tile's records, metric factors, static block, state and
@@ -243,18 +248,20 @@ __device__ __forceinline__ real wadg_second(const Lds<real, N> &L, const real *S
 // hybridized nodes (Section 2.6), written to out (tile-blocked [4][ne][Nh]: h~, u~, v~,
 // H~ - Href) or, in a resident stage that is not the last, straight into the node records
 // of the next stage (the same values the records phase would form from out):
-//   q = V_q u_h; h = eta_q + Href - b_q; v' = (g eta_q - |u|^2/2, u, v) = v(u_q) - (g Href, 0, 0)
+//   q = V_q u_h; h = eta_q + (Href - b_q); v' = (g eta_q - |u|^2/2, u, v) = v(u_q) - (g Href, 0, 0)
 //   (FP64); v'_h = Minv_k V_q^T diag(w J) v'_q (Minv_k the stored inverse, or the
 //   weight-adjusted one); v~' = V_h v'_h;
-//   H~ - Href = (v~1' + |v~23|^2/2)/g, h~ = Href + (H~ - Href) - b~ (FP64).
-// Subtracting the constant g Href is exact: the projection reproduces constants.
+//   H~ - Href = (v~1' + |v~23|^2/2)/g, h~ = (H~ - Href) + (Href - b~) (FP64).
+// Subtracting the constant g Href is exact: the projection reproduces constants.  The rest
+// depth Href - b comes from the static block, formed in double on the device from b (so in
+// float it has the relative accuracy of the depth itself where the water is shallow).
 template <typename real, int N, int CM, bool WADG>
 __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, Lds<real, N> &L, real *out,
                                              real *nbx_out, int32_t *flag, bool coherent, int res = 0) {
   const bool to_records = (res & kResident) && !(res & kResLast);
   constexpr bool mfma = CM != kValu;
   constexpr int Np = dim_Np(N), Nq = dim_Nq(N), Nh = dim_Nh(N), Nfq = dim_Nfq(N);
-  const double g = d.g, Href = d.Href;
+  const double g = d.g;
   const int tid = phase_tid(), nth = blockDim.x;
   const int nc = 3 * ne;                       // contraction columns: (field, element)
   real *Stage = L.R;                           // [3][ne][Nq] or [3][ne][Nh] staging (free here)
@@ -284,7 +291,7 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
       }
     }
     const double eta = u0, hu = u1, hv = u2;
-    const double h = eta + Href - double(L.bq[i]);
+    const double h = eta + double(L.bq[i]);       // L.bq: rest depth Href - b
     const double rh = 1.0 / h, uu = hu * rh, vv = hv * rh;
     const double v1 = g * eta - 0.5 * (uu * uu + vv * vv);
     const double w = L.wJ[i];
@@ -362,7 +369,7 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
     }
     const double v1 = t0, v2 = t1, v3 = t2;
     const double dH = (v1 + 0.5 * (v2 * v2 + v3 * v3)) / g;
-    const double h = Href + dH - double(L.bh[i]);
+    const double h = dH + double(L.bh[i]);        // L.bh: rest depth Href - b
     if (to_records) {
       typedef real real4 __attribute__((ext_vector_type(4)));
       const real hr = real(h), ur = real(v2), vr = real(v3), gr = real(d.g);
@@ -529,8 +536,8 @@ __device__ __forceinline__ void interface_terms(const real *rm, const real *nbp,
   t2 = wf * f2v;
 }
 
-template <typename real, int N, int R, int P, bool FACE>
-__device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int b, int p, Lds<real, N> &L, bool iface) {
+template <typename real, int N, int R, int P, bool FACE, class LT>
+__device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int b, int p, LT &L, bool iface) {
   constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
   // volume rows: all Nh columns (the diagonal of the skew operator is zero);
   // face rows: the Nq volume columns (the surface-surface block is zero)
@@ -603,12 +610,11 @@ __device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int 
 // Phase 2+3: residual rows.  A task is (element, block of R rows, column part p of P);
 // the P partial sums are added in the lift.  One flat task list: first every volume
 // task, then every face task, so whole waves take the same branch.
-template <typename real, int N, int R, int P>
-__device__ __forceinline__ void residual_tile(const InstDesc &d, int ne, Lds<real, N> &L, bool iface) {
+template <typename real, int N, int R, int P, class LT>
+__device__ __forceinline__ void residual_tile(const InstDesc &d, int ne, LT &L, bool iface) {
   constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N);
   constexpr int VB = Nq / R, FB = Nfq / R;
   static_assert(Nq % R == 0 && Nfq % R == 0, "R must divide Nq and Nfq");
-  static_assert(6 * dim_Nh(N) + 3 * dim_Np(N) <= 8 * dim_Nh(N) || P == 1, "partials must fit the raw block");
   const int tid = phase_tid(), nth = blockDim.x;
   const int nv = ne * VB * P, ntask = nv + ne * FB * P;
   for (int t = tid; t < ntask; t += nth) {
@@ -619,6 +625,48 @@ __device__ __forceinline__ void residual_tile(const InstDesc &d, int ne, Lds<rea
       const int tf = t - nv, p = tf % P, rest = tf / P, e = rest / FB;
       row_block<real, N, R, P, true>(d, ne, e, rest - e * FB, p, L, iface);
     }
+  }
+}
+
+// The residual phase in the instance's tile shape (one of the shapes of shape_ok).
+template <typename real, int N, class LT>
+__device__ __forceinline__ void residual_shaped(const InstDesc &d, int ne, LT &L, bool iface, int shape) {
+  switch (shape) {
+    case make_shape(1, 1): residual_tile<real, N, 1, 1>(d, ne, L, iface); break;
+    case make_shape(1, 2): residual_tile<real, N, 1, 2>(d, ne, L, iface); break;
+    case make_shape(1, 3): residual_tile<real, N, 1, 3>(d, ne, L, iface); break;
+    case make_shape(1, 4): residual_tile<real, N, 1, 4>(d, ne, L, iface); break;
+    default:
+      if constexpr (shape_ok<real, N>(make_shape(2, 1))) {
+        switch (shape) {
+          case make_shape(2, 1): residual_tile<real, N, 2, 1>(d, ne, L, iface); break;
+          case make_shape(2, 2): residual_tile<real, N, 2, 2>(d, ne, L, iface); break;
+          case make_shape(2, 3): residual_tile<real, N, 2, 3>(d, ne, L, iface); break;
+          case make_shape(2, 4): residual_tile<real, N, 2, 4>(d, ne, L, iface); break;
+          default: break;
+        }
+      }
+      break;
+  }
+}
+
+// Lift of the P partial residuals on the vector ALUs: T = V_h^T (sum_p R_p), one task per
+// (field, element, mode).
+template <typename real, int N, int P, class LT>
+__device__ __forceinline__ void lift_valu(int ne, LT &L) {
+  constexpr int Np = dim_Np(N), Nh = dim_Nh(N);
+  for (int i = phase_tid(); i < 3 * ne * Np; i += blockDim.x) {
+    const int c = (i >= ne * Np) + (i >= 2 * ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
+    const real *Rc = L.R + c * ne * Nh + e * Nh;
+    real ya = 0, yb = 0;
+#pragma unroll 4
+    for (int n = 0; n < Nh; ++n) {
+      real rn = Rc[n];
+#pragma unroll
+      for (int p = 1; p < P; ++p) rn += Rc[p * 3 * ne * Nh + n];
+      if (n & 1) yb += L.Vh[n * Np + j] * rn; else ya += L.Vh[n * Np + j] * rn;
+    }
+    L.T[i] = ya + yb;
   }
 }
 
@@ -669,8 +717,8 @@ __device__ __forceinline__ void publish(const StageArgs &a, int t, int value) {
 // part of the residual: W_f [ nJ . f_S(u~, u~+) + 1/2 g h (H+ - Href) nJ ] - LF penalty,
 // one task per (element, face node).  A separate pass so that a resident tile can run
 // the whole pair loop before it waits for its neighbours' values.
-template <typename real, int N>
-__device__ __forceinline__ void interface_tile(const InstDesc &d, int ne, Lds<real, N> &L) {
+template <typename real, int N, class LT>
+__device__ __forceinline__ void interface_tile(const InstDesc &d, int ne, LT &L) {
   constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
   for (int i = phase_tid(); i < ne * Nfq; i += blockDim.x) {
     const int e = i / Nfq, f = i - e * Nfq, m = Nq + f;
@@ -684,13 +732,18 @@ __device__ __forceinline__ void interface_tile(const InstDesc &d, int ne, Lds<re
   }
 }
 
-template <typename real, int N, int R, int CM, bool WADG, bool MULTI>
+// SHAPES: the build that takes the residual's tile shape from the instance (every shape of
+// shape_ok); without it, the default shape (RowsPerThread rows, two column parts), whose
+// register allocation the other shapes' code does not affect.
+template <typename real, int N, int CM, bool WADG, bool MULTI, bool SHAPES>
 __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm, real *tile,
                                            int res = 0, int t = 0, int target = 0) {
   constexpr int Np = dim_Np(N), Nh = dim_Nh(N), Nfq = dim_Nfq(N);
   const int tid = phase_tid(), nth = blockDim.x;
   constexpr int Nq = dim_Nq(N);
-  Lds<real, N> L(sm, tile, ne, mass_words(N, WADG));
+  const int shape = SHAPES ? d.shape : make_shape(RowsPerThread<real, N>::value, 2);
+  const int P = SHAPES ? shape_parts(shape) : 2;
+  Lds<real, N> L(sm, tile, ne, mass_words(N, WADG), P);
   const real g = real(d.g);
   const bool mid = res & kResMid;                // resident tile after its first stage
   const bool keep = (res & kResident) && !(res & kResLast);   // state stays in LDS only
@@ -730,7 +783,8 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
     rec[2] = real4{real(0.5) * g * h, dH, h, real(0)};
   }
   __syncthreads();
-  residual_tile<real, N, R, ColParts<N>::value>(d, ne, L, !mid);
+  if constexpr (SHAPES) residual_shaped<real, N>(d, ne, L, !mid, shape);
+  else residual_tile<real, N, RowsPerThread<real, N>::value, 2>(d, ne, L, !mid);
   if (!mid) {
     uint32_t *sl = reinterpret_cast<uint32_t *>(L.Minv);
 #pragma unroll
@@ -755,26 +809,23 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
   }
   __syncthreads();
   // lift: y = V_h^T r_h (r_h = sum of the P partials), one task per (field, element, mode)
-  constexpr bool mfma = CM != kValu;
   if constexpr (CM != kValu) {
-    {
-      constexpr int P = ColParts<N>::value;
-      gemm_mfma<CM, real>(Np, Nh, 3 * ne, [&](int i, int k) { return L.Vh[k * Np + i]; },
-                  [&](int k, int c) { return P > 1 ? L.R[c * Nh + k] + L.R[3 * ne * Nh + c * Nh + k] : L.R[c * Nh + k]; },
-                  [&](int i, int c, real v) { L.T[c * Np + i] = v; });
+    gemm_mfma<CM, real>(Np, Nh, 3 * ne, [&](int i, int k) { return L.Vh[k * Np + i]; },
+                        [&](int k, int c) {
+                          real v = L.R[c * Nh + k];
+                          for (int p = 1; p < P; ++p) v += L.R[p * 3 * ne * Nh + c * Nh + k];
+                          return v;
+                        },
+                        [&](int i, int c, real v) { L.T[c * Np + i] = v; });
+  } else if constexpr (SHAPES) {
+    switch (P) {
+      case 1: lift_valu<real, N, 1>(ne, L); break;
+      case 2: lift_valu<real, N, 2>(ne, L); break;
+      case 3: lift_valu<real, N, 3>(ne, L); break;
+      default: lift_valu<real, N, 4>(ne, L); break;
     }
-  }
-  for (int i = tid; i < 3 * ne * Np && !mfma; i += nth) {
-    const int c = (i >= ne * Np) + (i >= 2 * ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
-    const real *Rc = L.R + c * ne * Nh + e * Nh;
-    real ya = 0, yb = 0;
-#pragma unroll 4
-    for (int n = 0; n < Nh; ++n) {
-      real rn = Rc[n];
-      if (ColParts<N>::value > 1) rn += Rc[3 * ne * Nh + n];
-      if (n & 1) yb += L.Vh[n * Np + j] * rn; else ya += L.Vh[n * Np + j] * rn;
-    }
-    L.T[i] = ya + yb;
+  } else {
+    lift_valu<real, N, 2>(ne, L);
   }
   __syncthreads();
   // rhs = -Minv y; store it, or do the LSRK update
@@ -838,7 +889,11 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
 // tiles have finished the previous one (see wait_neighbours), which the co-residency of
 // all workgroups (cooperative launch) makes safe.  A wait that gives up sets flag bit 1
 // and ends the workgroup; its neighbours' waits then give up in turn.
-template <typename real, int CM, bool WADG, bool MULTI>
+// V1: the build that also holds the variant-1 element kinds (N+2 points per direction and
+// per face); launches whose instances are all of variant 0 use the build without them,
+// whose register allocation those larger kinds do not affect.  SHAPES: see stage_tile
+// (built with vector-ALU contractions and variant-0 kinds only).
+template <typename real, int CM, bool WADG, bool MULTI, bool V1, bool SHAPES>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel(StageArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -883,14 +938,21 @@ stage_kernel(StageArgs a) {
         loaded_N = d.N;
       }
       bool ok = true;
-      switch (d.N) {
-        case 1: ok = stage_tile<real, 1, RowsPerThread<real, 1>::value, CM, WADG, MULTI>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
-        case 2: ok = stage_tile<real, 2, RowsPerThread<real, 2>::value, CM, WADG, MULTI>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
-        case 3: ok = stage_tile<real, 3, RowsPerThread<real, 3>::value, CM, WADG, MULTI>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
-        case 4: ok = stage_tile<real, 4, RowsPerThread<real, 4>::value, CM, WADG, MULTI>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
-        case 5: ok = stage_tile<real, 5, RowsPerThread<real, 5>::value, CM, WADG, MULTI>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
-        default: break;
+#define ESDG_STAGE_CASE(D) \
+  case D: ok = stage_tile<real, D, CM, WADG, MULTI, SHAPES>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
+      if constexpr (V1) {
+        switch (d.N) {
+          ESDG_STAGE_CASE(1) ESDG_STAGE_CASE(2) ESDG_STAGE_CASE(3) ESDG_STAGE_CASE(4) ESDG_STAGE_CASE(5)
+          ESDG_STAGE_CASE(9) ESDG_STAGE_CASE(10) ESDG_STAGE_CASE(11) ESDG_STAGE_CASE(12) ESDG_STAGE_CASE(13)
+          default: break;
+        }
+      } else {
+        switch (d.N) {
+          ESDG_STAGE_CASE(1) ESDG_STAGE_CASE(2) ESDG_STAGE_CASE(3) ESDG_STAGE_CASE(4) ESDG_STAGE_CASE(5)
+          default: break;
+        }
       }
+#undef ESDG_STAGE_CASE
       if (!ok) {
         if (threadIdx.x == 0) atomicOr(a.flag, 2);
         return;
@@ -905,28 +967,35 @@ stage_kernel(StageArgs a) {
 }
 
 // FP64 diagnostics per tile: mass (3), entropy, entropy rate, sum |entropy-rate terms|.
-template <typename real, int N>
+// Everything but the state and the RHS (widened exactly from the bulk precision) is double:
+// V_q, w J and the bathymetry come from double copies kept for the diagnostics.
+template <typename real, int D>
 __device__ void diag_tile(const InstDesc &d, int k0, int ne, double *acc) {
-  constexpr int Np = dim_Np(N), Nq = dim_Nq(N);
-  const real *ref = static_cast<const real *>(d.ref);   // V_h rows 0..Nq-1 are V_q
+  constexpr int Np = dim_Np(D), Nq = dim_Nq(D), Nh = dim_Nh(D);
   const real *uh = static_cast<const real *>(d.uh);
   const real *rh = static_cast<const real *>(d.rhs_scratch);
-  const real *wJq = static_cast<const real *>(d.wJq);
-  const real *bq = static_cast<const real *>(d.bq);
+  const double *wJq = static_cast<const double *>(d.wJq);
   const size_t splane = size_t(d.K) * Np;
   const double g = d.g;
   for (int i = threadIdx.x; i < ne * Nq; i += blockDim.x) {
     const int e = i / Nq, q = i - e * Nq, k = k0 + e;
     double u[3] = {0, 0, 0}, r[3] = {0, 0, 0};
-    for (int j = 0; j < Np; ++j) {
-      const double v = ref[q * Np + j];
+    if constexpr (key_sbp(D)) {    // nodal state: the values at the volume nodes themselves
       for (int c = 0; c < 3; ++c) {
-        u[c] += v * double(uh[c * splane + size_t(k) * Np + j]);
-        r[c] += v * double(rh[c * splane + size_t(k) * Np + j]);
+        u[c] = double(uh[c * splane + size_t(k) * Np + q]);
+        r[c] = double(rh[c * splane + size_t(k) * Np + q]);
+      }
+    } else {
+      for (int j = 0; j < Np; ++j) {
+        const double v = d.Vqd[q * Np + j];
+        for (int c = 0; c < 3; ++c) {
+          u[c] += v * double(uh[c * splane + size_t(k) * Np + j]);
+          r[c] += v * double(rh[c * splane + size_t(k) * Np + j]);
+        }
       }
     }
-    const double w = wJq[size_t(k) * Nq + q], b = bq[size_t(k) * Nq + q];
-    const double h = u[0] + d.Href - b, uu = u[1] / h, vv = u[2] / h;
+    const double w = wJq[size_t(k) * Nq + q], b = d.bd[size_t(k) * Nh + q];
+    const double h = u[0] + (d.Href - b), uu = u[1] / h, vv = u[2] / h;
     acc[0] += w * h;
     acc[1] += w * u[1];
     acc[2] += w * u[2];
@@ -947,11 +1016,12 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagArgs a) {
   const InstDesc &d = read_const(a.desc, tl.inst);
   double acc[6] = {0, 0, 0, 0, 0, 0};
   switch (d.N) {
-    case 1: diag_tile<real, 1>(d, tl.k0, tl.ne, acc); break;
-    case 2: diag_tile<real, 2>(d, tl.k0, tl.ne, acc); break;
-    case 3: diag_tile<real, 3>(d, tl.k0, tl.ne, acc); break;
-    case 4: diag_tile<real, 4>(d, tl.k0, tl.ne, acc); break;
-    case 5: diag_tile<real, 5>(d, tl.k0, tl.ne, acc); break;
+#define ESDG_DIAG_CASE(D) \
+  case D: diag_tile<real, D>(d, tl.k0, tl.ne, acc); break;
+    ESDG_DIAG_CASE(1) ESDG_DIAG_CASE(2) ESDG_DIAG_CASE(3) ESDG_DIAG_CASE(4) ESDG_DIAG_CASE(5)
+    ESDG_DIAG_CASE(9) ESDG_DIAG_CASE(10) ESDG_DIAG_CASE(11) ESDG_DIAG_CASE(12) ESDG_DIAG_CASE(13)
+    ESDG_DIAG_CASE(17) ESDG_DIAG_CASE(18) ESDG_DIAG_CASE(19) ESDG_DIAG_CASE(20)
+#undef ESDG_DIAG_CASE
     default: break;
   }
   for (int c = 0; c < 6; ++c) red[threadIdx.x][c] = acc[c];
@@ -965,17 +1035,267 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagArgs a) {
     for (int c = 0; c < 6; ++c) a.partials[size_t(t) * 6 + c] = red[0][c];
 }
 
-// ---------------------------------------------------------------- host launchers
-
-template <bool WADG, bool MULTI>
-static const void *stage_fn_mode(bool fp64, int cm) {
-  if (fp64)
-    return cm == kMfmaNative ? reinterpret_cast<const void *>(&stage_kernel<double, kMfmaNative, WADG, MULTI>)
-                             : reinterpret_cast<const void *>(&stage_kernel<double, kValu, WADG, MULTI>);
-  if (cm == kMfmaBf16x3) return reinterpret_cast<const void *>(&stage_kernel<float, kMfmaBf16x3, WADG, MULTI>);
-  if (cm == kMfmaNative) return reinterpret_cast<const void *>(&stage_kernel<float, kMfmaNative, WADG, MULTI>);
-  return reinterpret_cast<const void *>(&stage_kernel<float, kValu, WADG, MULTI>);
+// The rest depth Href - b of every tile of an instance, rounded once from double into the
+// static block (Href changes at every set_state).  One workgroup per tile.
+template <typename real>
+__global__ void __launch_bounds__(kBlock) rest_depth_kernel(DiagArgs a) {
+  const int t = blockIdx.x;
+  if (t >= a.ntiles) return;
+  const Tile tl = read_const(a.tiles, t);
+  const InstDesc &d = read_const(a.desc, tl.inst);
+  const int D = d.N, Nq = dim_Nq(D), Nh = dim_Nh(D), ne = tl.ne;
+  const bool wadg = a.wadg != 0;
+  real *st = static_cast<real *>(const_cast<void *>(d.stat)) + size_t(tl.k0) * stat_words(D, wadg);
+  // modal kinds: Href - b at the volume nodes, then at the hybrid nodes, after the mass data
+  // and w J; DG-SBP: at the volume nodes, after 1/(w J)
+  real *dq = st + ne * (key_sbp(D) ? Nq : mass_words(D, wadg) + Nq);
+  real *dh = dq + ne * Nq;
+  for (int i = threadIdx.x; i < ne * Nq; i += blockDim.x) {
+    const int e = i / Nq, q = i - e * Nq;
+    dq[i] = real(d.Href - d.bd[size_t(tl.k0 + e) * Nh + q]);
+  }
+  if (!key_sbp(D))
+    for (int i = threadIdx.x; i < ne * Nh; i += blockDim.x) {
+      const int e = i / Nh, n = i - e * Nh;
+      dh[i] = real(d.Href - d.bd[size_t(tl.k0 + e) * Nh + n]);
+    }
 }
+
+// ---------------------------------------------------------------- DG-SBP (Section 3)
+// The DG-SBP scheme with traditional SBP operators obtained from the hybridized ones
+// (Section 3.2): Q_SBP = [I; I_f]^T Q_h [I; I_f] on a volume rule whose boundary nodes are
+// the face nodes, diagonal mass matrix W J, nodal state at the volume nodes, no entropy
+// projection.  Per element,
+//   (W J) du/dt = -[I; I_f]^T r_h,
+// where r_h is the hybridized residual of the modal kernel (skew form, zero block skipped,
+// folded source, interface terms) evaluated with the face values taken from the volume
+// nodes they coincide with: each face row is added to its volume node's row.
+
+// LDS carve-up of one DG-SBP tile (see tile_words()).
+template <typename real, int D>
+struct LdsSbp {
+  static constexpr int Nq = dim_Nq(D), Nfq = dim_Nfq(D), Nh = dim_Nh(D);
+  real *ref, *ST, *FT, *wf, *nr, *ns, *fvol, *vface;
+  real *rec, *R, *nb, *U, *DU, *iwJ, *dep, *geo;
+  int32_t *pp;
+  __device__ LdsSbp(real *sm, real *tile, int E) {
+    ref = sm;
+    ST = ref;
+    FT = ST + 2 * Nh * Nq;
+    wf = FT + 2 * Nq * Nfq;
+    nr = wf + Nfq;
+    ns = nr + Nfq;
+    fvol = ns + Nfq;              // volume node of face node f (integer-valued reals)
+    vface = fvol + Nfq;           // face node of volume node n, or -1
+    rec = tile;
+    R = rec + E * Nh * kNodeRec;  // two column-part partials [2][3][E][Nh]
+    nb = R + 6 * E * Nh;
+    U = nb + 4 * E * Nfq;
+    DU = U + 3 * E * Nq;
+    iwJ = DU + 3 * E * Nq;        // static block: 1/(w J) | rest depth | metrics [4][E][Nq] | push targets
+    dep = iwJ + E * Nq;
+    geo = dep + E * Nq;
+    pp = reinterpret_cast<int32_t *>(geo + 4 * E * Nq);
+  }
+};
+
+// Face values (h, u, v, H - Href) of the tile's state, pushed into the neighbours' slots (a
+// reflective wall node, Section 2.9, writes the mirror state into its own slot).
+template <typename real, int D>
+__device__ __forceinline__ void sbp_push(const InstDesc &d, int ne, LdsSbp<real, D> &L, real *nbx_out, int32_t *flag) {
+  constexpr int Nq = dim_Nq(D), Nfq = dim_Nfq(D);
+  bool bad = false;
+  for (int i = phase_tid(); i < ne * Nfq; i += blockDim.x) {
+    const int e = i / Nfq, f = i - e * Nfq, j = e * Nq + int(L.fvol[f]);
+    const double eta = L.U[j], hu = L.U[ne * Nq + j], hv = L.U[2 * ne * Nq + j];
+    const double h = eta + double(L.dep[j]);
+    const double u = hu / h, v = hv / h;
+    double pu = u, pv = v;
+    const uint32_t tgt = uint32_t(L.pp[i]);
+    if (tgt & kPushWall) {
+      const double nr = double(L.nr[f]), ns = double(L.ns[f]);
+      const double nx = double(L.geo[j]) * nr + double(L.geo[ne * Nq + j]) * ns;
+      const double ny = double(L.geo[2 * ne * Nq + j]) * nr + double(L.geo[3 * ne * Nq + j]) * ns;
+      const double c = 2.0 * (u * nx + v * ny) / (nx * nx + ny * ny);
+      pu = u - c * nx;
+      pv = v - c * ny;
+    }
+    typedef real real4 __attribute__((ext_vector_type(4)));
+    const real4 val = {real(h), real(pu), real(pv), real(eta)};
+    *reinterpret_cast<real4 *>(nbx_out + size_t(tgt & ~kPushWall) * 4) = val;
+    bad |= bad_value(h, hu, hv);
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+template <typename real, int D>
+__device__ __forceinline__ void sbp_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm, real *tile) {
+  constexpr int Nq = dim_Nq(D), Nfq = dim_Nfq(D), Nh = dim_Nh(D), SW = stat_words(D);
+  constexpr int W = sizeof(real) / 4;
+  LdsSbp<real, D> L(sm, tile, ne);
+  const int tid = phase_tid(), nth = blockDim.x;
+  const size_t splane = size_t(d.K) * Nq;
+  auto words = [](const void *p) { return static_cast<const uint32_t *>(p); };
+  auto lwords = [](real *p) { return reinterpret_cast<uint32_t *>(p); };
+  {                                // fetch: state, RK register, static block, neighbour values
+    const real *src = static_cast<const real *>(a.ext_state ? a.ext_state : d.uh);
+    const real *du = static_cast<const real *>(d.du);
+    for (int c = 0; c < 3; ++c) {
+      async_copy_words(lwords(L.U + c * ne * Nq), words(src + c * splane + size_t(k0) * Nq), ne * Nq * W);
+      if (a.mode == kStage)
+        async_copy_words(lwords(L.DU + c * ne * Nq), words(du + c * splane + size_t(k0) * Nq), ne * Nq * W);
+    }
+    async_copy_words(lwords(L.iwJ), words(static_cast<const real *>(d.stat) + size_t(k0) * SW), ne * SW * W);
+    if (a.mode != kProject) {
+      const void *nbx = a.ext_nbx ? a.ext_nbx : d.nbx[a.in_buf];
+      async_copy_words(lwords(L.nb), words(static_cast<const real *>(nbx) + size_t(k0) * Nfq * 4), ne * Nfq * 4 * W);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+  }
+  __syncthreads();
+  real *nbx_out = static_cast<real *>(a.ext_nbx ? a.ext_nbx : d.nbx[a.out_buf]);
+  if (a.mode == kProject) {
+    sbp_push<real, D>(d, ne, L, nbx_out, a.flag);
+    return;
+  }
+  // node records of the volume nodes, from the nodal state (h in double from eta and the
+  // rest depth; H - Href is eta itself)
+  const real g = real(d.g);
+  bool bad = false;
+  for (int i = tid; i < ne * Nq; i += nth) {
+    const double eta = L.U[i], hu = L.U[ne * Nq + i], hv = L.U[2 * ne * Nq + i];
+    const double h = eta + double(L.dep[i]);
+    const double u = hu / h, v = hv / h;
+    const int e = i / Nq, q = i - e * Nq;
+    typedef real real4 __attribute__((ext_vector_type(4)));
+    real4 *rec = reinterpret_cast<real4 *>(L.rec + (e * Nh + q) * kNodeRec);
+    rec[0] = real4{real(0.5 * hu), real(0.5 * hv), real(0.5 * u), real(0.5 * v)};
+    rec[1] = real4{L.geo[i], L.geo[ne * Nq + i], L.geo[2 * ne * Nq + i], L.geo[3 * ne * Nq + i]};
+    rec[2] = real4{real(0.5) * g * real(h), real(eta), real(h), real(0)};
+    bad |= bad_value(h, hu, hv);
+  }
+  if (bad) atomicOr(a.flag, 1);
+  __syncthreads();
+  // the face nodes' records are those of the volume nodes they coincide with
+  for (int i = tid; i < ne * Nfq * 3; i += nth) {
+    const int quad = i % 3, ef = i / 3, e = ef / Nfq, f = ef - e * Nfq;
+    typedef real real4 __attribute__((ext_vector_type(4)));
+    const real4 *srcr = reinterpret_cast<const real4 *>(L.rec + (e * Nh + int(L.fvol[f])) * kNodeRec);
+    reinterpret_cast<real4 *>(L.rec + (e * Nh + Nq + f) * kNodeRec)[quad] = srcr[quad];
+  }
+  __syncthreads();
+  residual_tile<real, D, 1, 2>(d, ne, L, true);
+  __syncthreads();
+  // du/dt = -(W J)^{-1} [I; I_f]^T r_h; store it, or do the LSRK update
+  real *uh = static_cast<real *>(d.uh);
+  real *du = static_cast<real *>(d.du);
+  real *rhs_out = static_cast<real *>(a.ext_rhs);
+  const real ra = real(a.rk_a), rdt = real(d.dt), rb = real(a.rk_b);
+  for (int i = tid; i < 3 * ne * Nq; i += nth) {
+    const int c = (i >= ne * Nq) + (i >= 2 * ne * Nq), j = i - c * ne * Nq, e = j / Nq, n = j - e * Nq;
+    const real *R0 = L.R + c * ne * Nh + e * Nh, *R1 = R0 + 3 * ne * Nh;
+    real r = R0[n] + R1[n];
+    const int vf = int(L.vface[n]);
+    if (vf >= 0) r += R0[Nq + vf] + R1[Nq + vf];
+    const real rr = -r * L.iwJ[j];
+    const size_t o = size_t(c) * splane + size_t(k0) * Nq + j;
+    if (a.mode == kRhs) {
+      rhs_out[o] = rr;
+    } else {
+      const real dn = ra * L.DU[i] + rdt * rr;
+      const real un = L.U[i] + rb * dn;
+      du[o] = dn;
+      uh[o] = un;
+      L.U[i] = un;
+    }
+  }
+  if (a.mode == kStage) {
+    __syncthreads();
+    sbp_push<real, D>(d, ne, L, nbx_out, a.flag);
+  }
+}
+
+// One launch per RK stage (or per projection / RHS) for every DG-SBP tile; persistent,
+// XCD-aligned chunks as in stage_kernel.
+template <typename real>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+sbp_stage_kernel(StageArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  real *sm = reinterpret_cast<real *>(smem_raw);
+  real *tile = sm + a.ref_words_max;
+  const int G = int(gridDim.x);
+  const int chunk = (int(blockIdx.x) % kXcds) * (G / kXcds) + int(blockIdx.x) / kXcds;
+  const int t0 = a.ranges ? read_const(a.ranges, chunk) : int((long long)chunk * a.ntiles / G);
+  const int t1 = a.ranges ? read_const(a.ranges, chunk + 1) : int((long long)(chunk + 1) * a.ntiles / G);
+  int loaded = 0;
+  for (int t = t0; t < t1; ++t) {
+    const Tile tl = read_const(a.tiles, t);
+    const InstDesc &d = read_const(a.desc, tl.inst);
+    if (d.N != loaded) {
+      __syncthreads();
+      const real *ref = static_cast<const real *>(d.ref);
+      const int words = ref_words(d.N);
+      for (int i = threadIdx.x; i < words; i += blockDim.x) sm[i] = ref[i];
+      loaded = d.N;
+    }
+    switch (d.N) {
+#define ESDG_SBP_CASE(N) \
+  case make_key(N, 2): sbp_tile<real, make_key(N, 2)>(a, d, tl.k0, tl.ne, sm, tile); break;
+      ESDG_SBP_CASE(1) ESDG_SBP_CASE(2) ESDG_SBP_CASE(3) ESDG_SBP_CASE(4)
+#undef ESDG_SBP_CASE
+      default: break;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- instantiation units
+// This file is compiled once per (precision, mass inverse) with ESDG_UNIT_REAL and
+// ESDG_UNIT_WADG defined, instantiating the stage kernels of that combination only, and
+// once with ESDG_UNIT_HOST for the DG-SBP, diagnostics and rest-depth kernels and the host
+// launchers; the five objects compile in parallel.  Each unit exports the stage kernels of
+// its combination by contraction mode and launch kind.
+#define ESDG_CAT4(a, b, c, d) a##b##c##d
+#define ESDG_UNIT_FN(R, W) ESDG_CAT4(stage_fn_unit_, R, _, W)
+const void *stage_fn_unit_float_0(int cm, bool multi, bool v1, bool shapes);
+const void *stage_fn_unit_float_1(int cm, bool multi, bool v1, bool shapes);
+const void *stage_fn_unit_double_0(int cm, bool multi, bool v1, bool shapes);
+const void *stage_fn_unit_double_1(int cm, bool multi, bool v1, bool shapes);
+
+#if defined(ESDG_UNIT_REAL)
+template <bool V1>
+static const void *unit_fn(int cm, bool multi) {
+  using real = ESDG_UNIT_REAL;
+  constexpr bool W = ESDG_UNIT_WADG != 0;
+  if constexpr (std::is_same<real, double>::value) {
+    if (cm == kMfmaNative)
+      return multi ? reinterpret_cast<const void *>(&stage_kernel<double, kMfmaNative, W, true, V1, false>)
+                   : reinterpret_cast<const void *>(&stage_kernel<double, kMfmaNative, W, false, V1, false>);
+    return multi ? reinterpret_cast<const void *>(&stage_kernel<double, kValu, W, true, V1, false>)
+                 : reinterpret_cast<const void *>(&stage_kernel<double, kValu, W, false, V1, false>);
+  } else {
+    if (cm == kMfmaBf16x3)
+      return multi ? reinterpret_cast<const void *>(&stage_kernel<float, kMfmaBf16x3, W, true, V1, false>)
+                   : reinterpret_cast<const void *>(&stage_kernel<float, kMfmaBf16x3, W, false, V1, false>);
+    if (cm == kMfmaNative)
+      return multi ? reinterpret_cast<const void *>(&stage_kernel<float, kMfmaNative, W, true, V1, false>)
+                   : reinterpret_cast<const void *>(&stage_kernel<float, kMfmaNative, W, false, V1, false>);
+    return multi ? reinterpret_cast<const void *>(&stage_kernel<float, kValu, W, true, V1, false>)
+                 : reinterpret_cast<const void *>(&stage_kernel<float, kValu, W, false, V1, false>);
+  }
+}
+const void *ESDG_UNIT_FN(ESDG_UNIT_REAL, ESDG_UNIT_WADG)(int cm, bool multi, bool v1, bool shapes) {
+  using real = ESDG_UNIT_REAL;
+  constexpr bool W = ESDG_UNIT_WADG != 0;
+  if (shapes)                      // vector-ALU contractions, variant-0 kinds
+    return multi ? reinterpret_cast<const void *>(&stage_kernel<real, kValu, W, true, false, true>)
+                 : reinterpret_cast<const void *>(&stage_kernel<real, kValu, W, false, false, true>);
+  return v1 ? unit_fn<true>(cm, multi) : unit_fn<false>(cm, multi);
+}
+#endif
+
+#if defined(ESDG_UNIT_HOST)
+// ---------------------------------------------------------------- host launchers
 
 // The stage kernel for a precision, contraction mode, mass inverse and launch kind (one
 // launch per stage, or all stages of a step call in one cooperative launch).  One launch
@@ -984,14 +1304,20 @@ static const void *stage_fn_mode(bool fp64, int cm) {
 // progress counts) was measured faster on balance (same box: N=4 1.4 %, N=5 5 %, the
 // mixed-degree ensemble 11 %; the per-stage build is faster only at N=3, by 8 %), while
 // the per-stage build is 7-11 % faster in FP64 and 6 % with split-bf16 contractions.
-static const void *stage_fn(bool fp64, int cm, bool wadg, bool multi) {
+static const void *stage_fn(bool fp64, int cm, bool wadg, bool multi, bool v1, bool shapes) {
   if (!fp64 && cm == kValu) multi = true;
-  if (wadg) return multi ? stage_fn_mode<true, true>(fp64, cm) : stage_fn_mode<true, false>(fp64, cm);
-  return multi ? stage_fn_mode<false, true>(fp64, cm) : stage_fn_mode<false, false>(fp64, cm);
+  if (fp64) return wadg ? stage_fn_unit_double_1(cm, multi, v1, shapes) : stage_fn_unit_double_0(cm, multi, v1, shapes);
+  return wadg ? stage_fn_unit_float_1(cm, multi, v1, shapes) : stage_fn_unit_float_0(cm, multi, v1, shapes);
 }
 
-// Workgroups of the stage kernel that stay resident on the whole device.
-hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, size_t lds_bytes, int *out) {
+static const void *sbp_fn(bool fp64) {
+  return fp64 ? reinterpret_cast<const void *>(&sbp_stage_kernel<double>)
+              : reinterpret_cast<const void *>(&sbp_stage_kernel<float>);
+}
+
+// Workgroups of the stage kernel (the DG-SBP kernel with sbp) that stay resident on the
+// whole device.
+hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, bool sbp, bool v1, bool shapes, size_t lds_bytes, int *out) {
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -1008,7 +1334,7 @@ hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, size_t lds_bytes, int 
   e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
   if (e != hipSuccess) return e;
   for (int multi = 0; multi < 2; ++multi) {
-    const void *fn = stage_fn(fp64, cm, wadg, multi != 0);
+    const void *fn = sbp ? sbp_fn(fp64) : stage_fn(fp64, cm, wadg, multi != 0, v1, shapes);
     int n = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kBlock, lds_bytes);
     if (e != hipSuccess) return e;
@@ -1024,11 +1350,13 @@ hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, size_t lds_bytes, int 
   return hipSuccess;
 }
 
-hipError_t set_stage_lds_limit(bool fp64, int cm, bool wadg, size_t lds_bytes) {
-  hipError_t e = hipFuncSetAttribute(stage_fn(fp64, cm, wadg, false), hipFuncAttributeMaxDynamicSharedMemorySize,
+hipError_t set_stage_lds_limit(bool fp64, int cm, bool wadg, bool sbp, bool v1, bool shapes, size_t lds_bytes) {
+  if (sbp) return hipFuncSetAttribute(sbp_fn(fp64), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
+  hipError_t e = hipFuncSetAttribute(stage_fn(fp64, cm, wadg, false, v1, shapes), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     int(lds_bytes));
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(stage_fn(fp64, cm, wadg, true), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
+  return hipFuncSetAttribute(stage_fn(fp64, cm, wadg, true, v1, shapes), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(lds_bytes));
 }
 
 // Persistent grid: at most max_blocks (what stays resident), at most one block per tile,
@@ -1039,13 +1367,13 @@ int stage_grid(int ntiles, int max_blocks) {
   return ((g + kXcds - 1) / kXcds) * kXcds;
 }
 
-hipError_t launch_stage(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream) {
+hipError_t launch_stage(bool fp64, bool sbp, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream) {
   if (a.ntiles <= 0) return hipSuccess;
   const int grid = stage_grid(a.ntiles, max_blocks);
   StageArgs arg = a;
   void *params[] = {&arg};
-  return hipLaunchKernel(stage_fn(fp64, a.contraction, a.wadg != 0, false), dim3(grid), dim3(kBlock), params,
-                         lds_bytes, stream);
+  return hipLaunchKernel(sbp ? sbp_fn(fp64) : stage_fn(fp64, a.contraction, a.wadg != 0, false, a.v1 != 0, a.shapes != 0), dim3(grid),
+                         dim3(kBlock), params, lds_bytes, stream);
 }
 
 // Multi-stage launch: every workgroup of the grid must be resident at once (tiles wait on
@@ -1055,7 +1383,7 @@ hipError_t launch_stage_fused(bool fp64, const StageArgs &a, int max_blocks, siz
   const int grid = stage_grid(a.ntiles, max_blocks);
   StageArgs arg = a;
   void *params[] = {&arg};
-  return hipLaunchCooperativeKernel(stage_fn(fp64, a.contraction, a.wadg != 0, true), dim3(grid), dim3(kBlock), params,
+  return hipLaunchCooperativeKernel(stage_fn(fp64, a.contraction, a.wadg != 0, true, a.v1 != 0, a.shapes != 0), dim3(grid), dim3(kBlock), params,
                                     lds_bytes, stream);
 }
 
@@ -1067,5 +1395,17 @@ hipError_t launch_diag(bool fp64, const DiagArgs &a, hipStream_t stream) {
     hipLaunchKernelGGL(diag_kernel<float>, dim3(a.ntiles), dim3(kBlock), 0, stream, a);
   return hipGetLastError();
 }
+
+// Rest depth of the tiles a.tiles[0 .. a.ntiles) (one instance's) into their static blocks.
+hipError_t launch_rest_depth(bool fp64, const DiagArgs &a, hipStream_t stream) {
+  if (a.ntiles <= 0) return hipSuccess;
+  if (fp64)
+    hipLaunchKernelGGL(rest_depth_kernel<double>, dim3(a.ntiles), dim3(kBlock), 0, stream, a);
+  else
+    hipLaunchKernelGGL(rest_depth_kernel<float>, dim3(a.ntiles), dim3(kBlock), 0, stream, a);
+  return hipGetLastError();
+}
+
+#endif  // ESDG_UNIT_HOST
 
 }  // namespace esdg

@@ -211,6 +211,19 @@ def basin(n: int = 64, N: int = 3, wall: float = 0.15, dam: float = 0.2, width: 
     return w
 
 
+def near_dry(n: int = 8, N: int = 3, hmin: float = 1e-3, speed: float = 0.05, steps: int = 5) -> Workload:
+    """Shallow water over a bump: the config-2 mesh, b = 0.2 + 0.1 sin(pi x) sin(pi y) (0.1 to
+    0.3), free surface level 0.3 + hmin (depth hmin over the bump's top, about 0.2 elsewhere),
+    moving water u = speed cos(pi y), v = speed sin(pi x), LF flux."""
+    xg, yg, xf, yf = structured_mesh(n, N, warp=0.05)
+    b = 0.2 + 0.1 * np.sin(np.pi * xf) * np.sin(np.pi * yf)
+    h = 0.3 + hmin - b
+    u = speed * np.cos(np.pi * yf)
+    v = speed * np.sin(np.pi * xf)
+    return _mk("near_dry", n, N, 0.05, 1.0, b, h, h * u, h * v, "lf", 0.25, steps, "fp32", 0, xg, yg, xf, yf,
+               meta={"hmin": hmin})
+
+
 def _fourier(rng, x, y, nmodes, amax, kmax=4):
     out = np.zeros_like(x)
     for _ in range(nmodes):

@@ -59,3 +59,35 @@ def check_rhs(r_gpu: np.ndarray, r_ref: np.ndarray, bound: np.ndarray, eps: floa
 
 EPS32 = 2.0 ** -24
 EPS64 = 2.0 ** -53
+
+
+def sbp_rhs_abs_bound(o: "O.SBPOracle", u: np.ndarray) -> np.ndarray:
+    """The same bound for the DG-SBP scheme (Section 3.2): the absolute terms of
+    sum_i (2 Q_SBP^i o F^i) 1 + source + I_f^T (interface terms), divided by w J (the
+    diagonal mass matrix).  u: nodal state [3, K, Nq]."""
+    d, ref, g = o.d, o.d.ref, o.d.g
+    ks = np.arange(d.K)
+    Qx, Qy = o.Q_sbp(ks)
+    uL = tuple(u[c][:, :, None] for c in range(3))
+    uR = tuple(u[c][:, None, :] for c in range(3))
+    Fx, Fy = O.ec_flux(uL, uR, g)
+    r = np.zeros_like(u)
+    for c in range(3):
+        r[c] = 2.0 * np.sum(np.abs(Qx) * np.abs(Fx[c]) + np.abs(Qy) * np.abs(Fy[c]), axis=2)
+    bq = np.abs(d.b_q)
+    r[1] += g * np.abs(u[0]) * np.einsum("kmn,kn->km", np.abs(Qx), bq)
+    r[2] += g * np.abs(u[0]) * np.einsum("kmn,kn->km", np.abs(Qy), bq)
+    uh = u[:, :, np.r_[np.arange(ref.Nq), o.If]]
+    uf = uh[:, :, ref.Nq:]
+    up = O.exterior_state(d, uh, ks)
+    fS_x, fS_y = O.ec_flux(tuple(up), tuple(uf), g)
+    f_x, f_y = O.physical_flux(uf[0], uf[1], uf[2], g)
+    nJx, nJy, sJ = np.abs(d.nJx), np.abs(d.nJy), d.sJ
+    speed = lambda v: np.abs(v[1] / v[0]) + np.abs(v[2] / v[0]) + np.sqrt(g * np.abs(v[0]))
+    lam = np.maximum(speed(uf), speed(up))
+    sel = np.eye(ref.Nq)[o.If]
+    for c in range(3):
+        t = ref.wf[None] * (nJx * (np.abs(fS_x[c]) + np.abs(f_x[c])) + nJy * (np.abs(fS_y[c]) + np.abs(f_y[c])) +
+                            0.5 * lam * sJ * (np.abs(up[c]) + np.abs(uf[c])))
+        r[c] += t @ sel
+    return r / (ref.wq[None, :] * d.Jq)[None]

@@ -44,7 +44,7 @@ def _init(lib, w, precision=1, flux=1, g=1.0, epb=0, xg=None):
         opt.precision = precision
     h = C.c_void_p()
     nb = C.c_size_t()
-    st = lib.esdg_swe_init(1, arr, C.byref(opt), C.byref(h), C.byref(nb))
+    st = lib.esdg_swe_init(1, arr, None, C.byref(opt), C.byref(h), C.byref(nb))
     return st, h, nb.value, lib.esdg_swe_last_error(None).decode()
 
 
@@ -105,7 +105,7 @@ def test_init_weight_adjusted_mass():
         arr[0] = binding.esdg_swe_instance(w.N, w.K, binding._dptr(xg), binding._dptr(yg), binding._dptr(b), w.Lx, w.Ly)
         opt = binding.make_options("fp32", "lf", 1.0, True, 0, mass=mass)
         h, nb = C.c_void_p(), C.c_size_t()
-        assert lib.esdg_swe_init(1, arr, C.byref(opt), C.byref(h), C.byref(nb)) == binding.ESDG_OK
+        assert lib.esdg_swe_init(1, arr, None, C.byref(opt), C.byref(h), C.byref(nb)) == binding.ESDG_OK
         sizes[mass] = nb.value
         lib.esdg_swe_destroy(h)
     Np, Nq = 21, 36
@@ -115,7 +115,7 @@ def test_init_weight_adjusted_mass():
     arr = (binding.esdg_swe_instance * 1)()
     arr[0] = binding.esdg_swe_instance(w.N, w.K, binding._dptr(xg), binding._dptr(yg), binding._dptr(b), w.Lx, w.Ly)
     h, nb = C.c_void_p(), C.c_size_t()
-    assert lib.esdg_swe_init(1, arr, C.byref(opt), C.byref(h), C.byref(nb)) == binding.ESDG_EINVAL
+    assert lib.esdg_swe_init(1, arr, None, C.byref(opt), C.byref(h), C.byref(nb)) == binding.ESDG_EINVAL
 
 
 def test_init_walls():
@@ -129,7 +129,7 @@ def test_init_walls():
         arr[0] = binding.esdg_swe_instance(w.N, w.K, binding._dptr(xg), binding._dptr(yg), binding._dptr(b), L, L)
         opt = binding.make_options("fp32", "lf", 1.0, True, 0)
         h, nb = C.c_void_p(), C.c_size_t()
-        st = lib.esdg_swe_init(1, arr, C.byref(opt), C.byref(h), C.byref(nb))
+        st = lib.esdg_swe_init(1, arr, None, C.byref(opt), C.byref(h), C.byref(nb))
         assert st == expect, lib.esdg_swe_last_error(None).decode()
         if st == binding.ESDG_OK:
             lib.esdg_swe_destroy(h)
@@ -149,7 +149,7 @@ def test_empty_and_out_of_range_inputs():
         arr[0] = binding.esdg_swe_instance(N, K, binding._dptr(xg), binding._dptr(yg), binding._dptr(b), w.Lx, w.Ly)
         opt = binding.make_options("fp32", "lf", 1.0, True, epb)
         h, nb = C.c_void_p(), C.c_size_t()
-        st = lib.esdg_swe_init(n_inst, arr, C.byref(opt), C.byref(h), C.byref(nb))
+        st = lib.esdg_swe_init(n_inst, arr, None, C.byref(opt), C.byref(h), C.byref(nb))
         if st == binding.ESDG_OK:
             lib.esdg_swe_destroy(h)
         return st
@@ -165,3 +165,83 @@ def test_empty_and_out_of_range_inputs():
                              (1, binding.ESDG_FP64, 257, 4), (2, binding.ESDG_FP32, 10, 4)):
         assert lib.esdg_volume_kernel(kind, prec, dummy, dummy, dummy, dummy, n, K, C.c_double(9.81), None) \
             == binding.ESDG_EINVAL, (kind, n, K)
+
+
+def _init_quad(lib, w, quad, scheme="modal", precision="fp32"):
+    keep = []
+    xg, yg, b = (np.ascontiguousarray(a) for a in (w.xg, w.yg, w.b_nodes))
+    arr = (binding.esdg_swe_instance * 1)()
+    arr[0] = binding.esdg_swe_instance(w.N, w.K, binding._dptr(xg), binding._dptr(yg), binding._dptr(b), w.Lx, w.Ly)
+    qarr = (binding.esdg_swe_quadrature * 1)()
+    qarr[0] = binding.make_quadrature(quad, keep)
+    opt = binding.make_options(precision, "lf", 1.0, True, 0, scheme=scheme)
+    h = C.c_void_p()
+    nb = C.c_size_t()
+    st = lib.esdg_swe_init(1, arr, qarr, C.byref(opt), C.byref(h), C.byref(nb))
+    out = (C.c_int32 * 6)()
+    if st == 0:
+        assert lib.esdg_swe_query(h, 0, out) == 0
+        lib.esdg_swe_destroy(h)
+    return st, lib.esdg_swe_last_error(None).decode(), list(out)
+
+
+def test_init_quadrature_choices():
+    """Section 2.1 quadrature at the boundary: the default rules, the Stroud rule with N+2
+    points per direction and N+2 face points, a caller's rule (padded to the compiled node
+    count), and the DG-SBP rules (Section 3.1) are accepted; the sizes follow."""
+    from oracle import esdg_oracle as O
+    from paper_2005_02516_amd import sbp_rules
+    lib = binding.load_library()
+    for N in (1, 3, 5):
+        w = wl.config2(n=2, N=N)
+        st, msg, out = _init_quad(lib, w, None)
+        assert st == 0 and out[3] == (N + 1) ** 2 and out[4] == 3 * (N + 1), msg
+        st, msg, out = _init_quad(lib, w, {"vol_degree": 2 * N + 2, "face_points": N + 2})
+        assert st == 0 and out[3] == (N + 2) ** 2 and out[4] == 3 * (N + 2), msg
+        st, msg, out = _init_quad(lib, w, {"face_points": N + 2})      # (N+1)^2 Stroud nodes, padded
+        assert st == 0 and out[3] == (N + 2) ** 2, msg
+        r, s, q = O.stroud_rule(N)
+        st, msg, out = _init_quad(lib, w, {"rule": (s, r, q)})
+        assert st == 0 and out[3] == (N + 1) ** 2, msg
+    w = wl.config2(n=2, N=1)                     # the 3-point edge-midpoint rule (degree 2), padded to 4
+    st, msg, out = _init_quad(lib, w, {"rule": ([0.0, 0.0, -1.0], [-1.0, 0.0, 0.0], [2 / 3] * 3)})
+    assert st == 0 and out[3] == 4, msg
+    st, msg, out = _init_quad(lib, w, {"rule": ([-1.0, 1.0, -1.0], [-1.0, -1.0, 1.0], [2 / 3] * 3)})
+    assert st == binding.ESDG_EINVAL, msg       # the vertex rule is exact only to degree 1
+    for N in (1, 2, 3, 4):
+        w = wl.config2(n=2, N=N)
+        st, msg, out = _init_quad(lib, w, {"rule": sbp_rules.load(N)}, scheme="sbp")
+        assert st == 0 and out[2] == out[3] == {1: 6, 2: 10, 3: 18, 4: 22}[N], msg
+
+
+def test_init_quadrature_rejected():
+    """Rules that fail Section 2.1's (or 3.1's) conditions are refused with ESDG_EINVAL."""
+    from oracle import esdg_oracle as O
+    from paper_2005_02516_amd import sbp_rules
+    lib = binding.load_library()
+    N = 2
+    w = wl.config2(n=2, N=N)
+    r, s, q = O.stroud_rule(N)
+    bad = {
+        "not exact": {"rule": (r, s, q * np.r_[1.01, np.ones(q.size - 1)])},
+        "negative weight": {"rule": (np.r_[r, -0.5], np.r_[s, -0.5], np.r_[q, -1e-3])},
+        "outside": {"rule": (np.r_[r, 0.5], np.r_[s, 0.5], np.r_[q, 0.0])},
+        "degree above 2N+3": {"vol_degree": 2 * N + 4},
+        "degree below 2N": {"vol_degree": 2 * N - 1},
+        "face points": {"face_points": N + 3},
+        "too many nodes": {"rule": O.stroud_rule(N, N + 3)},
+        "(N+2)^2 nodes with N+1 face points": {"vol_degree": 2 * N + 2},
+    }
+    for name, quad in bad.items():
+        st, msg, _ = _init_quad(lib, w, quad)
+        assert st == binding.ESDG_EINVAL, (name, msg)
+    # DG-SBP: the rule must contain the face nodes, have the compiled size, and N <= 4
+    st, msg, _ = _init_quad(lib, w, {"rule": (r, s, q)}, scheme="sbp")
+    assert st == binding.ESDG_EINVAL, msg
+    st, msg, _ = _init_quad(lib, w, None, scheme="sbp")
+    assert st == binding.ESDG_EINVAL, msg
+    w5 = wl.config2(n=2, N=5)
+    st, msg, _ = _init_quad(lib, w5, {"rule": sbp_rules.load(4)}, scheme="sbp")
+    assert st == binding.ESDG_EINVAL, msg
+    st, msg, _ = _init_quad(lib, w, {"rule": sbp_rules.load(N)}, scheme="sbp", precision="bf16x3")
+    assert st == binding.ESDG_EINVAL, msg
