@@ -124,7 +124,7 @@ def test_ensemble_subset(torch_mod):
             err_h = np.array([np.linalg.norm(u_gpu[c] - u_ref[c]) / hn for c in range(3)])
             print(f"ensemble instance {pick[j]} N={w.N} K={w.K}: 1-step rel L2 {err} (by ||h||: {err_h})",
                   flush=True)
-            assert err[0] < 1e-5 and np.all(err_h < 1e-5), (pick[j], err, err_h)
+            assert np.all(err < 1e-5), (pick[j], err, err_h)
         ks = np.sort(np.random.default_rng(j).choice(w.K, size=128, replace=False))
         r_ref = o.rhs(s.get_state(j), ks)
         import torch

@@ -17,6 +17,7 @@ sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 
 from oracle import esdg_oracle as O
 from paper_2005_02516_amd import workloads as wl
+from parity_util import EPS32, EPS64, check_rhs, rhs_abs_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -84,10 +85,12 @@ def test_rhs_fp64(torch, name, make, flux):
     s.sync()
     r_gpu = rhs.cpu().numpy()
     r_ref = o.rhs(uh_gpu)
-    # relative to max |rhs| per field: the dense form's own rounding (cancelling pressure
-    # terms of size g h H) is ~1e-13..1e-12 of that, so the bar for one RHS is 1e-11
-    err = rel_field_err(r_gpu, r_ref)
-    assert np.all(err < 1e-11), err
+    # every entry within 64 eps of the forward rounding bound of its own sum (the RHS of a
+    # near-balanced state is a small difference of large pressure terms)
+    ok, worst = check_rhs(r_gpu, r_ref, rhs_abs_bound(o, uh_gpu, np.arange(w.K)), EPS64)
+    print(f"{name} {flux} fp64: per-field max err / max|rhs| {rel_field_err(r_gpu, r_ref)}, "
+          f"worst err / (eps * bound) {worst:.2f}", flush=True)
+    assert ok, worst
     s.close()
 
 
@@ -103,9 +106,11 @@ def test_rhs_fp32(torch, name, make):
     s.rhs(0, st, rhs)
     s.sync()
     r_ref = o.rhs(uh32)
-    scale = max(np.abs(r_ref).max(), 1e-3)
-    err = rel_field_err(rhs.cpu().double().numpy(), r_ref, scale=scale)
-    assert np.all(err < 2e-5), err
+    r_gpu = rhs.cpu().double().numpy()
+    ok, worst = check_rhs(r_gpu, r_ref, rhs_abs_bound(o, uh32, np.arange(w.K)), EPS32)
+    print(f"{name} fp32: per-field max err / max|rhs| {rel_field_err(r_gpu, r_ref)}, "
+          f"worst err / (eps * bound) {worst:.2f}", flush=True)
+    assert ok, worst
     s.close()
 
 
@@ -175,12 +180,10 @@ def test_fp32_100_steps_small(torch):
     s.close()
     u_ref, _ = O.run(o, uh0, w.dt, 100)
     hn = np.linalg.norm(u_ref[0])
-    err = np.array([np.linalg.norm(u_gpu[0] - u_ref[0]) / hn,
-                    np.linalg.norm(u_gpu[1] - u_ref[1]) / max(np.linalg.norm(u_ref[1]), 1e-300),
-                    np.linalg.norm(u_gpu[2] - u_ref[2]) / max(np.linalg.norm(u_ref[2]), 1e-300)])
+    err = np.array([np.linalg.norm(u_gpu[c] - u_ref[c]) / np.linalg.norm(u_ref[c]) for c in range(3)])
     err_h = np.array([np.linalg.norm(u_gpu[c] - u_ref[c]) / hn for c in range(3)])
-    print("fp32 100-step rel-L2 per field:", err, "normalised by ||h||:", err_h, flush=True)
-    assert err[0] < 1e-5 and np.all(err_h < 1e-5), (err, err_h)
+    print("fp32 100-step rel-L2 per field (own norms):", err, "normalised by ||h||:", err_h, flush=True)
+    assert np.all(err < 1e-5), err
 
 
 def test_diagnostics_parity(torch):
@@ -217,9 +220,10 @@ def test_ragged_tiles_and_small_meshes(torch):
         rhs = torch.empty_like(st)
         s.rhs(0, st, rhs)
         s.sync()
-        err = rel_field_err(rhs.cpu().numpy(), o.rhs(s.get_state(0)), scale=1.0)
+        uh = s.get_state(0)
+        ok, worst = check_rhs(rhs.cpu().numpy(), o.rhs(uh), rhs_abs_bound(o, uh, np.arange(w.K)), EPS64)
         s.close()
-        assert np.all(err < 1e-11), (n, N, epb, err)
+        assert ok, (n, N, epb, worst)
 
 
 def test_large_tiles(torch):
@@ -235,9 +239,10 @@ def test_large_tiles(torch):
         rhs = torch.empty_like(st)
         s.rhs(0, st, rhs)
         s.sync()
-        err = rel_field_err(rhs.cpu().numpy(), o.rhs(s.get_state(0)), scale=1.0)
+        uh = s.get_state(0)
+        ok, worst = check_rhs(rhs.cpu().numpy(), o.rhs(uh), rhs_abs_bound(o, uh, np.arange(w.K)), EPS64)
         s.close()
-        assert np.all(err < 1e-11), (n, N, epb, err)
+        assert ok, (n, N, epb, worst)
         ref = _run_steps([w], "fp32", 3, fused=False, elems_per_block=epb)
         got = _run_steps([w], "fp32", 3, fused=True, elems_per_block=epb)
         assert all(np.array_equal(a, b) for a, b in zip(ref, got)), (n, N, epb)
