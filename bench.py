@@ -4,10 +4,12 @@
 Workload (N=3, the degree the metric is quoted at): periodic [0,2]^2, 64x64 squares split
 into 8192 curved triangles (nodes warped by 0.05 sin(pi x) sin(pi y)), bathymetry
 b = 0.1 sin(pi x) cos(pi y) + 0.1, lake at rest H = 2.2 plus a seeded Gaussian bump of
-amplitude 0.01, Lax-Friedrichs interface flux, g = 1.  A step is one LSRK4(5) step
-(five fused RK-stage launches, replayed from HIP graphs); inputs are resident in HBM
-before the timed region.  value = K * Np / (time per RK stage), FP32 bulk path with FP64
-entropy round trip; the FP64 path is timed on the same workload for the speedup.
+amplitude 0.01, Lax-Friedrichs interface flux, g = 1.  A step is one LSRK4(5) step (five
+RK stages); the library's automatic plan runs all stages of a step call in one cooperative
+launch when every tile gets a resident workgroup (this mesh in FP32), else one launch per
+stage replayed from HIP graphs.  Inputs are resident in HBM before the timed region.
+value = K * Np / (time per RK stage), FP32 bulk path with FP64 entropy round trip; the
+FP64 path is timed on the same workload for the speedup.
 
 Prints one JSON line.  Only one GPU is supported: --gpus > 1 exits with a message.
 """
@@ -88,9 +90,11 @@ def kernel_source_hash():
 
 def measured_traffic(w, prec, epb, step_mode, stages_per_launch):
     """HBM bytes per RK stage (FETCH_SIZE and WRITE_SIZE, copy-calibrated) from a committed
-    counter summary taken for this kernel source, workload, tile size, launch mode and number
-    of stages per launch (a multi-stage launch spreads its first fetch and last write over
-    its stages), or None when there is none."""
+    counter summary taken for this kernel source, workload, tile size and launch mode, or
+    None when there is none.  A one-launch-per-stage summary gives the bytes of one stage.
+    A multi-stage summary gives a fixed part (the first stage's full fetch, the last one's
+    write-back) and a per-stage part, fitted from launches of two stage counts, so the
+    bytes per stage of a launch of S stages are fixed / S + per_stage."""
     for path in TRAFFIC_FILES:
         if not os.path.exists(path):
             continue
@@ -102,13 +106,18 @@ def measured_traffic(w, prec, epb, step_mode, stages_per_launch):
                     kv[k] = v
         if kv.get("kernel_source_sha256") != kernel_source_hash() or int(kv.get("step_mode", -1)) != step_mode:
             continue
-        if int(kv.get("stages_per_launch", -1)) != stages_per_launch:
-            continue
         if (int(kv.get("N", -1)), int(kv.get("K", -1)), kv.get("precision"), int(kv.get("epb", -1))) != \
                 (w.N, w.K, prec, epb):
             continue
-        return {"fetch": int(kv["fetch_bytes"]), "write": int(kv["write_bytes"]),
-                "source": os.path.relpath(path, ROOT)}
+        if "per_stage_fetch_bytes" in kv:
+            S = float(stages_per_launch)
+            fetch = float(kv["fixed_fetch_bytes"]) / S + float(kv["per_stage_fetch_bytes"])
+            write = float(kv["fixed_write_bytes"]) / S + float(kv["per_stage_write_bytes"])
+        elif int(kv.get("stages_per_launch", -1)) == stages_per_launch:
+            fetch, write = float(kv["fetch_bytes"]), float(kv["write_bytes"])
+        else:
+            continue
+        return {"fetch": int(round(fetch)), "write": int(round(write)), "source": os.path.relpath(path, ROOT)}
     return None
 
 
@@ -141,39 +150,84 @@ def time_steps(s, dt, steps, torch):
     return ev0.elapsed_time(ev1)
 
 
-def cpu_baseline(w, stages_budget=75, mass="stored", stages_all_cores=25):
-    """The FP64 oracle as it stands, timed on this host: `stages_budget` RK stages of the
-    same workload (one RHS + axpy each), BLAS pinned to one thread; then `stages_all_cores`
-    stages with BLAS allowed up to 16 threads (the host share of one GPU; numpy's
-    elementwise work stays on one thread either way)."""
-    from threadpoolctl import threadpool_info, threadpool_limits
+_POOL_ORACLE = None
+
+
+def _pool_init(w, mass, Href):
+    """Worker of the CPU baseline: its own oracle for the workload, BLAS on one thread."""
+    global _POOL_ORACLE
+    from threadpoolctl import threadpool_limits
+    from oracle import esdg_oracle as O
+    threadpool_limits(1)
+    d = O.Discretization(w.N, w.xg, w.yg, w.b_nodes, w.g, w.Lx, w.Ly, mass="wadg" if mass == "wadg" else "exact")
+    _POOL_ORACLE = O.Oracle(d, w.flux, Href=Href)
+
+
+def _pool_rhs(args):
+    uh, ks = args
+    return _POOL_ORACLE.rhs(uh, ks)
+
+
+def host_cpu():
+    """(usable cores, CPU model) of this host."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return n, model
+
+
+def cpu_baseline(w, stages_pool=50, mass="stored", stages_single=25, max_workers=16):
+    """The FP64 oracle as it stands, timed on this host's cores: the RK stages of the same
+    workload with each stage's right-hand side split into element chunks over a process
+    pool (one worker per core, at most the host share of one GPU, 16; each worker calls the
+    oracle's rhs on its chunk, which projects the whole state and evaluates its chunk's rows;
+    the main process adds the chunks and does the LSRK axpy).  Also a one-core run (BLAS on
+    one thread) for reference."""
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
     from oracle import esdg_oracle as O
     d = O.Discretization(w.N, w.xg, w.yg, w.b_nodes, w.g, w.Lx, w.Ly, mass="wadg" if mass == "wadg" else "exact")
     uh0 = d.interpolate(w.u_nodes)
-    o = O.Oracle(d, w.flux, Href=O.mean_free_surface(d, uh0))
+    Href = O.mean_free_surface(d, uh0)
+    o = O.Oracle(d, w.flux, Href=Href)
     Np = dims(w.N)[0]
+    ncores, model = host_cpu()
+    P = max(1, min(max_workers, ncores))
+    chunks = np.array_split(np.arange(w.K), P)
 
-    def timed(stages, threads):
+    def rk(stages, rhs):
         uh, du = uh0.copy(), np.zeros_like(uh0)
-        with threadpool_limits(threads):
-            used = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-            t0 = time.perf_counter()
-            for s in range(stages):
-                du = O.LSRK_A[s % 5] * du + w.dt * o.rhs(uh)
-                uh = uh + O.LSRK_B[s % 5] * du
-            return time.perf_counter() - t0, used
+        t0 = time.perf_counter()
+        for s in range(stages):
+            du = O.LSRK_A[s % 5] * du + w.dt * rhs(uh)
+            uh = uh + O.LSRK_B[s % 5] * du
+        return time.perf_counter() - t0
 
-    t, _ = timed(stages_budget, 1)
-    out = {"value": w.K * Np * stages_budget / t, "unit": "DOF-updates/s per RK stage", "cores": 1,
-           "kind": "oracle",
-           "sample": f"{stages_budget} RK stages ({stages_budget // 5} LSRK steps) of the same {w.K}-element N={w.N} "
-                     f"workload, dense FP64 numpy oracle, BLAS limited to 1 thread, {t:.1f} s"}
-    if stages_all_cores:
-        ta, used = timed(stages_all_cores, min(16, os.cpu_count() or 1))
-        out["multi_thread"] = {"value": w.K * Np * stages_all_cores / ta, "cores": used,
-                               "sample": f"{stages_all_cores} RK stages of the same workload, BLAS up to {used} "
-                                         f"threads, {ta:.1f} s"}
-    return out
+    with mp.get_context("fork").Pool(P, initializer=_pool_init, initargs=(w, mass, Href)) as pool:
+        def rhs_pool(uh):
+            parts = pool.map(_pool_rhs, [(uh, ks) for ks in chunks])
+            return np.concatenate(parts, axis=1)
+        rk(1, rhs_pool)                         # workers built and warm
+        t = rk(stages_pool, rhs_pool)
+    with threadpool_limits(1):
+        t1 = rk(stages_single, o.rhs)
+    return {"value": w.K * Np * stages_pool / t, "unit": "DOF-updates/s per RK stage", "cores": P, "kind": "oracle",
+            "sample": f"{stages_pool} RK stages ({stages_pool // 5} LSRK steps) of the same {w.K}-element N={w.N} "
+                      f"workload, dense FP64 numpy oracle, each stage's RHS over {P} worker processes by element "
+                      f"chunks, {t:.1f} s",
+            "host": {"nproc": ncores, "cpu_model": model},
+            "single_core": {"value": w.K * Np * stages_single / t1, "cores": 1,
+                            "sample": f"{stages_single} RK stages, one process, BLAS on one thread, {t1:.1f} s"}}
 
 
 # FLOPs per matrix entry and element in the Section 5.4 volume terms: traditional, 2 matrices x
@@ -451,7 +505,8 @@ def main():
                                 if args.walls else "curved periodic lake at rest + Gaussian bump, ") +
                                f"{args.n}x{args.n}x2={w.K} triangles, "
                                f"N={w.N} (Np={Np}, Nq={Nq}, Nfq={Nfq}), LF flux, LSRK4(5)",
-                   "K": w.K, "N": w.N, "DOF": dof, "precision": prec, "hip_graph": not args.no_graph,
+                   "K": w.K, "N": w.N, "DOF": dof, "precision": prec,
+                   "hip_graph": (not args.no_graph) and plans[prec]["step_mode"] == 0,
                    "elements_per_workgroup": epb_used.get(prec, 0),
                    "matrix_cores": bool(args.matrix_cores or prec == "bf16x3"),
                    "mass_inverse": {"stored": "stored per element", "wadg": "weight-adjusted"}[args.mass],
