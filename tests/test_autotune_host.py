@@ -24,8 +24,13 @@ def test_cache_entries_well_formed():
         N = int(nn[1:])
         assert prec in ("fp32", "fp64") and 1 <= N <= 5 and cls in ("S", "M", "L"), key
         assert A.size_class(e["K"]) == cls, key
-        assert e["epb"] in A.CANDIDATES and A.lds_ok(N, e["epb"], prec), key
-        assert str(e["epb"]) in e["us_per_stage"], key          # the chosen size was timed
+        P = e.get("parts", 2)
+        assert e["epb"] in A.CANDIDATES and A.lds_ok(N, e["epb"], prec, P), key
+        if "rows" in e:                                          # the chosen (E, R, P) was timed
+            assert (e["rows"], e["parts"]) in A.shapes(N, prec), key
+            assert f'{e["epb"]}:{e["rows"]}:{e["parts"]}' in e["shape_us_per_stage"], key
+        else:
+            assert str(e["epb"]) in e["us_per_stage"], key          # the chosen size was timed
 
 
 def test_lookup_size_classes():
@@ -66,13 +71,13 @@ def test_parse_cases():
         A.parse_cases("6:64")
 
 
-def _init_status(lib, w, prec, E):
+def _init_status(lib, w, prec, E, shape=None):
     xg, yg, b = (np.ascontiguousarray(a) for a in (w.xg, w.yg, w.b_nodes))
     arr = (binding.esdg_swe_instance * 1)()
     arr[0] = binding.esdg_swe_instance(w.N, w.K, binding._dptr(xg), binding._dptr(yg), binding._dptr(b), w.Lx, w.Ly)
-    opt = binding.make_options(prec, "lf", 1.0, True, {w.N: E})
+    opt = binding.make_options(prec, "lf", 1.0, True, {w.N: E}, shape={w.N: shape} if shape else None)
     h, nb = C.c_void_p(), C.c_size_t()
-    st = lib.esdg_swe_init(1, arr, C.byref(opt), C.byref(h), C.byref(nb))
+    st = lib.esdg_swe_init(1, arr, None, C.byref(opt), C.byref(h), C.byref(nb))
     if st == binding.ESDG_OK:
         lib.esdg_swe_destroy(h)
     return st
@@ -91,3 +96,34 @@ def test_lds_model_matches_library_limit(prec):
         assert _init_status(lib, w, prec, emax) == binding.ESDG_OK, (N, emax)
         if emax < 64:
             assert _init_status(lib, w, prec, emax + 1) == binding.ESDG_EINVAL, (N, emax + 1)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_shapes_match_library(prec):
+    """Every (R, P) the tuner searches is accepted by the library, other shapes are refused,
+    and the LDS model with P column parts agrees with the library's 160 KiB limit."""
+    lib = binding.load_library()
+    word = 8 if prec == "fp64" else 4
+    for N in range(1, 6):
+        w = wl.config2(n=2, N=N)
+        ok = A.shapes(N, prec)
+        for R in (1, 2, 3):
+            for P in (1, 2, 3, 4, 5):
+                st = _init_status(lib, w, prec, 1, A.shape_code(R, P))
+                assert (st == binding.ESDG_OK) == ((R, P) in ok), (N, R, P, st)
+        for R, P in ok:
+            fits = [E for E in range(1, 65) if (A.ref_words(N) + A.tile_words(N, E, P)) * word <= 160 * 1024]
+            emax = max(fits)
+            assert _init_status(lib, w, prec, emax, A.shape_code(R, P)) == binding.ESDG_OK, (N, R, P, emax)
+            if emax < 64:
+                assert _init_status(lib, w, prec, emax + 1, A.shape_code(R, P)) == binding.ESDG_EINVAL, (N, R, P)
+
+
+def test_lookup_shapes_defaults_without_entry():
+    e, shp = A.lookup_shapes("fp32", [(3, 8192)])
+    assert e == A.lookup("fp32", [(3, 8192)])
+    c = _cache()["fp32:N3:S"]
+    if "rows" in c:
+        assert shp == {3: A.shape_code(c["rows"], c["parts"])}
+    else:
+        assert shp is None
