@@ -67,7 +67,7 @@ def shape_code(R: int, P: int) -> int:
 
 def default_shape(N: int, precision: str) -> Tuple[int, int]:
     """The library's default (R, P)."""
-    return (2 if precision != "fp64" and N in (1, 3) else 1), 2
+    return (2 if precision != "fp64" and N in (1, 3) else 1), (3 if precision != "fp64" and N == 5 else 2)
 
 
 def shapes(N: int, precision: str) -> List[Tuple[int, int]]:
@@ -91,7 +91,7 @@ def fit_mixed(precision: str, epb: Dict[int, int], shp: Optional[Dict[int, int]]
     if len(epb) < 2:
         return dict(epb)
     word = 8 if precision == "fp64" else 4
-    parts = {N: ((shp or {}).get(N, 2) & 15) for N in epb}
+    parts = {N: ((shp or {}).get(N, 0) & 15) or default_shape(N, precision)[1] for N in epb}
     ref_max = max(ref_words(N) for N in epb)
     alone = max((ref_words(N) + tile_words(N, E, parts[N])) * word + STATIC_LDS for N, E in epb.items())
     budget = max(LDS_FOUR_PER_CU, alone)
@@ -109,14 +109,18 @@ def lookup(precision: str, sizes: Iterable[Tuple[int, int]]) -> Optional[Dict[in
     return lookup_shapes(precision, sizes)[0]
 
 
-def lookup_shapes(precision: str, sizes: Iterable[Tuple[int, int]]):
+def lookup_shapes(precision: str, sizes: Iterable[Tuple[int, int]], valu: bool = True):
     """(E per degree, packed tile shape per degree) for instances of (N, K), or (None,
     None) without cache entries; a degree whose entry has no shape gets the library's
-    default.  Mixed degrees: E fitted to the shared LDS (fit_mixed)."""
+    default.  The shapes were timed on single-degree workloads with vector-ALU
+    contractions, so a launch of several degrees, the split-bf16 mode or matrix-core
+    contractions (valu False) take the default shape and the best E timed with it; several degrees then have E fitted to the shared
+    LDS (fit_mixed)."""
     cache = _load().get("entries", {})
     totals: Dict[int, int] = {}
     for N, K in sizes:
         totals[N] = totals.get(N, 0) + K
+    own_shape = len(totals) == 1 and precision != "bf16x3" and valu
     out, shp = {}, {}
     order = {"S": ("S", "M", "L"), "M": ("M", "L", "S"), "L": ("L", "M", "S")}
     for N, K in totals.items():
@@ -125,9 +129,14 @@ def lookup_shapes(precision: str, sizes: Iterable[Tuple[int, int]]):
             e = next((cache[f"{prec}:N{N}:{cls}"] for cls in order[size_class(K)]
                       if f"{prec}:N{N}:{cls}" in cache), None)
             if e:
-                out[N] = int(e["epb"])
-                if "rows" in e:
+                if "rows" in e and own_shape:
+                    out[N] = int(e["epb"])
                     shp[N] = shape_code(int(e["rows"]), int(e["parts"]))
+                elif "rows" in e:           # the fastest E with the default shape
+                    t = e["us_per_stage"]
+                    out[N] = int(min(t, key=lambda E: t[E]))
+                else:
+                    out[N] = int(e["epb"])
                 break
     if not out:
         return None, None
@@ -154,7 +163,10 @@ def time_config(w, precision: str, epb: int, steps: int = 4, warmup: int = 1, sh
         s.close()
 
 
-def lds_ok(N: int, E: int, precision: str, P: int = 2) -> bool:
+def lds_ok(N: int, E: int, precision: str, P: Optional[int] = None) -> bool:
+    """The tile of E elements fits the LDS with P column chunks (default: the library's
+    default shape)."""
+    P = default_shape(N, precision)[1] if P is None else P
     Nh = (N + 1) ** 2 + 3 * (N + 1)
     word = 8 if precision == "fp64" else 4
     return (ref_words(N) + tile_words(N, E, P)) * word <= 160 * 1024 and E * Nh <= 2048

@@ -177,13 +177,14 @@ class EsdgSwe:
         for i, spec in enumerate(quadrature):
             qarr[i] = make_quadrature(spec, self._keep)
         default_rules = scheme == "modal" and not any(quadrature)
-        if not elems_per_block and tuned and default_rules:   # the tuning cache covers the default rules
-            from .autotune import lookup_shapes
-            elems_per_block, tuned_shape = lookup_shapes(precision, [(w.N, w.K) for w in instances])
-            if tile_shape is None:
-                tile_shape = tuned_shape
         if matrix_cores is None:
             matrix_cores = os.environ.get("ESDG_SWE_MATRIX_CORES", "0") == "1"
+        if not elems_per_block and tuned and default_rules:   # the tuning cache covers the default rules
+            from .autotune import lookup_shapes
+            elems_per_block, tuned_shape = lookup_shapes(precision, [(w.N, w.K) for w in instances],
+                                                         valu=not matrix_cores)
+            if tile_shape is None:
+                tile_shape = tuned_shape
         if fused is None:       # one launch per step call when tiles can stay resident
             fused = {"0": False, "1": True}.get(os.environ.get("ESDG_SWE_FUSED", ""), "auto")
         self.elems_per_block = elems_per_block

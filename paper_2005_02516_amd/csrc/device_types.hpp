@@ -91,6 +91,15 @@ __host__ __device__ constexpr int shape_rows(int shape) { return shape >> 4; }
 __host__ __device__ constexpr int shape_parts(int shape) { return shape & 15; }
 __host__ __device__ constexpr int make_shape(int R, int P) { return (R << 4) | P; }
 
+// Balanced column chunks of the residual phase (the kinds with many hybrid nodes; see
+// kernels.hip): volume rows (Nh columns) are cut into P chunks of residual_chunk columns
+// (the last one shorter), and face rows (Nq columns) into chunks of the same length,
+// residual_face_parts of them, so that every task runs about as many columns.
+__host__ __device__ constexpr int residual_chunk(int D, int P) { return (dim_Nh(D) + P - 1) / P; }
+__host__ __device__ constexpr int residual_face_parts(int D, int P) {
+  return (dim_Nq(D) + residual_chunk(D, P) - 1) / residual_chunk(D, P);
+}
+
 // Reals per element of the block that holds the fetched u~ and metric factors [8][Nh]
 // (dead after the node records) and then the P residual partials [P][3][Nh] and the lift's
 // output [3][Np].

@@ -188,6 +188,10 @@ struct Lds {
 template <typename real, int N> struct RowsPerThread { static constexpr int value = 1; };
 template <> struct RowsPerThread<float, 1> { static constexpr int value = 2; };
 template <> struct RowsPerThread<float, 3> { static constexpr int value = 2; };
+// Default column chunks of the residual phase: three in float at N = 5 (whose volume rows
+// then split into chunks as long as the face rows' two), else two.
+template <typename real, int N> struct DefaultParts { static constexpr int value = 2; };
+template <> struct DefaultParts<float, 5> { static constexpr int value = 3; };
 
 // Tile shapes the residual phase is compiled for: R = 1 or 2 rows per thread (2 only in
 // float, where R divides Nq and Nfq: two rows of double accumulators exceed the register
@@ -536,22 +540,21 @@ __device__ __forceinline__ void interface_terms(const real *rm, const real *nbp,
   t2 = wf * f2v;
 }
 
-template <typename real, int N, int R, int P, bool FACE, class LT>
-__device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int b, int p, LT &L, bool iface) {
-  constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
-  // volume rows: all Nh columns (the diagonal of the skew operator is zero);
-  // face rows: the Nq volume columns (the surface-surface block is zero)
-  constexpr int NCOL = FACE ? Nq : Nh;
-  const int n_lo = p * NCOL / P, n_hi = (p + 1) * NCOL / P;   // this task's column range
-  constexpr int LD = FACE ? Nfq : Nq;
-  const int r0 = b * R;                       // first row within the row set
-  const int m0 = FACE ? Nq + r0 : r0;         // first hybrid-node index
-  const real *Stab = FACE ? L.FT : L.ST;
+// Residual rows (Section 2.8, flux differencing plus interface terms).  Row m accumulates,
+// over its columns n, c = Qx {hu} + Qy {hv} (a0), u_n c and v_n c (b1, b2), and dH_n Qx,
+// dH_n Qy (q1, q2); the row factors are applied once at the end:
+//   sum_n ({u} c + gh_m dH_n Qx) = u_m a0 + b1 + gh_m q1   (halves folded into the records)
+// Volume rows run over all Nh columns (the diagonal of the skew operator is zero), face rows
+// over the Nq volume columns (the surface-surface block is zero).  This function is one
+// task: rows m0 .. m0+R-1 (r0 .. r0+R-1 within their row set) of element e, over columns
+// [n_lo, n_hi), with the operator table Stab (already offset to row r0) whose consecutive
+// columns are ld2 reals apart; the sums go to chunk slot p of the residual block.
+template <typename real, int N, int R, class LD, class LT>
+__device__ __forceinline__ void row_sums(const InstDesc &d, int ne, int e, int r0, int m0, int p, bool face,
+                                         int n_lo, int n_hi, const real *Stab, LD ld2, LT &L, bool iface) {
+  constexpr int Nfq = dim_Nfq(N), Nh = dim_Nh(N);
   typedef real real4 __attribute__((ext_vector_type(4)));
   const real *rbase = L.rec + e * Nh * kNodeRec;
-  // Row m accumulates, over its columns n, c = Qx {hu} + Qy {hv} (a0), u_n c and v_n c (b1,
-  // b2), and dH_n Qx, dH_n Qy (q1, q2); the row factors are applied once at the end:
-  //   sum_n ({u} c + gh_m dH_n Qx) = u_m a0 + b1 + gh_m q1   (halves folded into the records)
   real hu[R], hv[R], u[R], v[R], gh[R], rx[R], sx[R], ry[R], sy[R], a0[R], a1[R], a2[R];
   real b1[R], b2[R], q1[R], q2[R];
 #pragma unroll
@@ -569,7 +572,7 @@ __device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int 
     const real4 c0 = *reinterpret_cast<const real4 *>(rn), c1 = *reinterpret_cast<const real4 *>(rn + 4);
     const real hun = c0.x, hvn = c0.y, un = c0.z, vn = c0.w, dHn = rn[9];
     const real rxn = c1.x, sxn = c1.y, ryn = c1.z, syn = c1.w;
-    const real *S = Stab + (n * LD + r0) * 2;
+    const real *S = Stab + n * ld2;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const real Sr = S[2 * r], Ss = S[2 * r + 1];
@@ -591,7 +594,7 @@ __device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int 
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int m = m0 + r;
-    if (FACE && p == 0 && iface) {         // interface terms of face row m (else a later pass)
+    if (face && p == 0 && iface) {         // interface terms of face row m (else a later pass)
       const int f = r0 + r;
       real t0, t1, t2;
       interface_terms<real>(rbase + m * kNodeRec, L.nb + (e * Nfq + f) * 4, L.wf[f], L.nr[f], L.ns[f], real(d.g),
@@ -600,30 +603,61 @@ __device__ __forceinline__ void row_block(const InstDesc &d, int ne, int e, int 
       a1[r] = a1[r] + t1;
       a2[r] = a2[r] + t2;
     }
-    real *Rp = L.R + p * 3 * ne * Nh;     // partial sums of column part p
+    real *Rp = L.R + p * 3 * ne * Nh;     // partial sums of column chunk p
     Rp[0 * ne * Nh + e * Nh + m] = a0[r];
     Rp[1 * ne * Nh + e * Nh + m] = a1[r];
     Rp[2 * ne * Nh + e * Nh + m] = a2[r];
   }
 }
 
-// Phase 2+3: residual rows.  A task is (element, block of R rows, column part p of P);
-// the P partial sums are added in the lift.  One flat task list: first every volume
-// task, then every face task, so whole waves take the same branch.
+// Two task layouts for the residual rows.  Kinds with few hybrid nodes cut volume and face
+// rows each into P chunks, and their tasks fill separate waves (volume tasks first), each
+// row type with its own compile-time loop.  Kinds with many (wide_kind) cut both row
+// types into chunks of one length (residual_chunk), so that volume and face tasks sharing
+// a wave run about the same trip count through one loop; the chunk partials are then
+// summed once (sum_partials) instead of in every lift task.
+template <int D> __host__ __device__ constexpr bool wide_kind() { return dim_Nh(D) >= 50; }
+template <int D, int P> __host__ __device__ constexpr int face_chunks() {
+  return wide_kind<D>() ? residual_face_parts(D, P) : P;
+}
+
 template <typename real, int N, int R, int P, class LT>
 __device__ __forceinline__ void residual_tile(const InstDesc &d, int ne, LT &L, bool iface) {
-  constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N);
-  constexpr int VB = Nq / R, FB = Nfq / R;
+  constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
+  constexpr int VB = Nq / R, FB = Nfq / R, PF = face_chunks<N, P>();
   static_assert(Nq % R == 0 && Nfq % R == 0, "R must divide Nq and Nfq");
   const int tid = phase_tid(), nth = blockDim.x;
-  const int nv = ne * VB * P, ntask = nv + ne * FB * P;
+  const int nv = ne * VB * P, ntask = nv + ne * FB * PF;
   for (int t = tid; t < ntask; t += nth) {
-    if (t < nv) {
-      const int p = t % P, rest = t / P, e = rest / VB;
-      row_block<real, N, R, P, false>(d, ne, e, rest - e * VB, p, L, iface);
+    if constexpr (wide_kind<N>()) {
+      constexpr int C = residual_chunk(N, P);
+      const bool face = t >= nv;
+      int p, e, b;
+      if (face) {
+        const int tt = t - nv, rest = tt / PF;
+        p = tt - rest * PF;
+        e = rest / FB;
+        b = rest - e * FB;
+      } else {
+        const int rest = t / P;
+        p = t - rest * P;
+        e = rest / VB;
+        b = rest - e * VB;
+      }
+      const int ncol = face ? Nq : Nh, n_lo = p * C, n_hi = n_lo + C < ncol ? n_lo + C : ncol;
+      const int r0 = b * R;
+      row_sums<real, N, R>(d, ne, e, r0, face ? Nq + r0 : r0, p, face, n_lo, n_hi,
+                           (face ? L.FT : L.ST) + 2 * r0, face ? 2 * Nfq : 2 * Nq, L, iface);
     } else {
-      const int tf = t - nv, p = tf % P, rest = tf / P, e = rest / FB;
-      row_block<real, N, R, P, true>(d, ne, e, rest - e * FB, p, L, iface);
+      if (t < nv) {
+        const int p = t % P, rest = t / P, e = rest / VB, r0 = (rest - e * VB) * R;
+        row_sums<real, N, R>(d, ne, e, r0, r0, p, false, p * Nh / P, (p + 1) * Nh / P, L.ST + 2 * r0,
+                             std::integral_constant<int, 2 * Nq>(), L, iface);
+      } else {
+        const int tf = t - nv, p = tf % P, rest = tf / P, e = rest / FB, r0 = (rest - e * FB) * R;
+        row_sums<real, N, R>(d, ne, e, r0, Nq + r0, p, true, p * Nq / P, (p + 1) * Nq / P, L.FT + 2 * r0,
+                             std::integral_constant<int, 2 * Nfq>(), L, iface);
+      }
     }
   }
 }
@@ -650,9 +684,29 @@ __device__ __forceinline__ void residual_shaped(const InstDesc &d, int ne, LT &L
   }
 }
 
-// Lift of the P partial residuals on the vector ALUs: T = V_h^T (sum_p R_p), one task per
-// (field, element, mode).
+// Wide kinds: adds the chunk partial sums of every residual row into chunk 0's (P chunks
+// for volume rows, face_chunks for face rows), once per (field, element, node), so that
+// the lift reads one partial.
 template <typename real, int N, int P, class LT>
+__device__ __forceinline__ void sum_partials(int ne, LT &L) {
+  constexpr int Nq = dim_Nq(N), Nh = dim_Nh(N), PF = face_chunks<N, P>();
+  for (int i = phase_tid(); i < 3 * ne * Nh; i += blockDim.x) {
+    const int n = i % Nh;
+    real r = L.R[i];
+    if (n < Nq) {
+#pragma unroll
+      for (int p = 1; p < P; ++p) r += L.R[p * 3 * ne * Nh + i];
+    } else {
+#pragma unroll
+      for (int p = 1; p < PF; ++p) r += L.R[p * 3 * ne * Nh + i];
+    }
+    L.R[i] = r;
+  }
+}
+
+// Lift of the residual on the vector ALUs: T = V_h^T r_h, one task per (field, element,
+// mode).  PS partial sums per row are added here (1 once sum_partials has run).
+template <typename real, int N, int PS, class LT>
 __device__ __forceinline__ void lift_valu(int ne, LT &L) {
   constexpr int Np = dim_Np(N), Nh = dim_Nh(N);
   for (int i = phase_tid(); i < 3 * ne * Np; i += blockDim.x) {
@@ -663,10 +717,33 @@ __device__ __forceinline__ void lift_valu(int ne, LT &L) {
     for (int n = 0; n < Nh; ++n) {
       real rn = Rc[n];
 #pragma unroll
-      for (int p = 1; p < P; ++p) rn += Rc[p * 3 * ne * Nh + n];
+      for (int p = 1; p < PS; ++p) rn += Rc[p * 3 * ne * Nh + n];
       if (n & 1) yb += L.Vh[n * Np + j] * rn; else ya += L.Vh[n * Np + j] * rn;
     }
     L.T[i] = ya + yb;
+  }
+}
+
+// The residual's chunk partials reduced to what the lift reads: summed in place for wide
+// kinds (then a barrier), left for the lift otherwise.
+template <typename real, int N, int P, int CM, class LT>
+__device__ __forceinline__ void lift_partials(int ne, LT &L) {
+  constexpr int Np = dim_Np(N), Nh = dim_Nh(N);
+  if constexpr (wide_kind<N>() && P > 1) {
+    sum_partials<real, N, P>(ne, L);
+    __syncthreads();
+  }
+  constexpr int PS = wide_kind<N>() ? 1 : P;
+  if constexpr (CM != kValu) {
+    gemm_mfma<CM, real>(Np, Nh, 3 * ne, [&](int i, int k) { return L.Vh[k * Np + i]; },
+                        [&](int k, int c) {
+                          real v = L.R[c * Nh + k];
+                          for (int p = 1; p < PS; ++p) v += L.R[p * 3 * ne * Nh + c * Nh + k];
+                          return v;
+                        },
+                        [&](int i, int c, real v) { L.T[c * Np + i] = v; });
+  } else {
+    lift_valu<real, N, PS>(ne, L);
   }
 }
 
@@ -733,16 +810,16 @@ __device__ __forceinline__ void interface_tile(const InstDesc &d, int ne, LT &L)
 }
 
 // SHAPES: the build that takes the residual's tile shape from the instance (every shape of
-// shape_ok); without it, the default shape (RowsPerThread rows, two column parts), whose
-// register allocation the other shapes' code does not affect.
+// shape_ok); without it, the default shape (RowsPerThread rows, DefaultParts column chunks),
+// whose register allocation the other shapes' code does not affect.
 template <typename real, int N, int CM, bool WADG, bool MULTI, bool SHAPES>
 __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d, int k0, int ne, real *sm, real *tile,
                                            int res = 0, int t = 0, int target = 0) {
   constexpr int Np = dim_Np(N), Nh = dim_Nh(N), Nfq = dim_Nfq(N);
   const int tid = phase_tid(), nth = blockDim.x;
   constexpr int Nq = dim_Nq(N);
-  const int shape = SHAPES ? d.shape : make_shape(RowsPerThread<real, N>::value, 2);
-  const int P = SHAPES ? shape_parts(shape) : 2;
+  const int shape = SHAPES ? d.shape : make_shape(RowsPerThread<real, N>::value, DefaultParts<real, N>::value);
+  const int P = SHAPES ? shape_parts(shape) : DefaultParts<real, N>::value;
   Lds<real, N> L(sm, tile, ne, mass_words(N, WADG), P);
   const real g = real(d.g);
   const bool mid = res & kResMid;                // resident tile after its first stage
@@ -784,7 +861,7 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
   }
   __syncthreads();
   if constexpr (SHAPES) residual_shaped<real, N>(d, ne, L, !mid, shape);
-  else residual_tile<real, N, RowsPerThread<real, N>::value, 2>(d, ne, L, !mid);
+  else residual_tile<real, N, RowsPerThread<real, N>::value, DefaultParts<real, N>::value>(d, ne, L, !mid);
   if (!mid) {
     uint32_t *sl = reinterpret_cast<uint32_t *>(L.Minv);
 #pragma unroll
@@ -808,24 +885,17 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
     interface_tile<real, N>(d, ne, L);
   }
   __syncthreads();
-  // lift: y = V_h^T r_h (r_h = sum of the P partials), one task per (field, element, mode)
-  if constexpr (CM != kValu) {
-    gemm_mfma<CM, real>(Np, Nh, 3 * ne, [&](int i, int k) { return L.Vh[k * Np + i]; },
-                        [&](int k, int c) {
-                          real v = L.R[c * Nh + k];
-                          for (int p = 1; p < P; ++p) v += L.R[p * 3 * ne * Nh + c * Nh + k];
-                          return v;
-                        },
-                        [&](int i, int c, real v) { L.T[c * Np + i] = v; });
-  } else if constexpr (SHAPES) {
+  // lift: y = V_h^T r_h (r_h = the sum of the chunk partials), one task per (field, element,
+  // mode)
+  if constexpr (SHAPES) {
     switch (P) {
-      case 1: lift_valu<real, N, 1>(ne, L); break;
-      case 2: lift_valu<real, N, 2>(ne, L); break;
-      case 3: lift_valu<real, N, 3>(ne, L); break;
-      default: lift_valu<real, N, 4>(ne, L); break;
+      case 1: lift_partials<real, N, 1, CM>(ne, L); break;
+      case 2: lift_partials<real, N, 2, CM>(ne, L); break;
+      case 3: lift_partials<real, N, 3, CM>(ne, L); break;
+      default: lift_partials<real, N, 4, CM>(ne, L); break;
     }
   } else {
-    lift_valu<real, N, 2>(ne, L);
+    lift_partials<real, N, DefaultParts<real, N>::value, CM>(ne, L);
   }
   __syncthreads();
   // rhs = -Minv y; store it, or do the LSRK update
@@ -1196,7 +1266,10 @@ __device__ __forceinline__ void sbp_tile(const StageArgs &a, const InstDesc &d, 
     const real *R0 = L.R + c * ne * Nh + e * Nh, *R1 = R0 + 3 * ne * Nh;
     real r = R0[n] + R1[n];
     const int vf = int(L.vface[n]);
-    if (vf >= 0) r += R0[Nq + vf] + R1[Nq + vf];
+    if (vf >= 0) {                 // face rows have face_chunks<D, 2>() chunk partials
+      r += R0[Nq + vf];
+      if constexpr (face_chunks<D, 2>() > 1) r += R1[Nq + vf];
+    }
     const real rr = -r * L.iwJ[j];
     const size_t o = size_t(c) * splane + size_t(k0) * Nq + j;
     if (a.mode == kRhs) {

@@ -95,12 +95,15 @@ int default_epb(int D, size_t word, bool wadg, int P) {
   return best;
 }
 
-// Default tile shape of the residual phase: two rows per thread in float at N = 1 and 3 of
-// the default quadrature, else one; two column parts.  (DG-SBP tiles use one row and two
-// parts always.)
+// Default tile shape of the residual phase (kernels.hip: RowsPerThread, DefaultParts): two
+// rows per thread in float at N = 1 and 3 of the default quadrature, else one; three column
+// chunks in float at N = 5 of the default quadrature, else two.  (DG-SBP tiles use one row
+// and two chunks always.)
 int default_shape(int D, bool fp64) {
-  const bool two = !fp64 && key_variant(D) == 0 && (key_N(D) == 1 || key_N(D) == 3);
-  return make_shape(two ? 2 : 1, 2);
+  const bool v0 = !fp64 && key_variant(D) == 0;
+  const bool two = v0 && (key_N(D) == 1 || key_N(D) == 3);
+  const bool three = v0 && key_N(D) == 5;
+  return make_shape(two ? 2 : 1, three ? 3 : 2);
 }
 
 // A tile shape the stage kernel is compiled for (kernels.hip: shape_ok).

@@ -24,7 +24,7 @@ def test_cache_entries_well_formed():
         N = int(nn[1:])
         assert prec in ("fp32", "fp64") and 1 <= N <= 5 and cls in ("S", "M", "L"), key
         assert A.size_class(e["K"]) == cls, key
-        P = e.get("parts", 2)
+        P = e.get("parts", A.default_shape(N, prec)[1])
         assert e["epb"] in A.CANDIDATES and A.lds_ok(N, e["epb"], prec, P), key
         if "rows" in e:                                          # the chosen (E, R, P) was timed
             assert (e["rows"], e["parts"]) in A.shapes(N, prec), key
@@ -53,14 +53,15 @@ def test_fit_mixed_budget(prec):
     tuned = A.lookup(prec, [(2, 8192), (3, 8192), (4, 8192)])
     fitted = A.fit_mixed(prec, tuned)
     ref_max = max(A.ref_words(N) for N in fitted)
-    alone = max((A.ref_words(N) + A.tile_words(N, E)) * word + A.STATIC_LDS for N, E in tuned.items())
+    P = {N: A.default_shape(N, prec)[1] for N in tuned}
+    alone = max((A.ref_words(N) + A.tile_words(N, E, P[N])) * word + A.STATIC_LDS for N, E in tuned.items())
     budget = max(A.LDS_FOUR_PER_CU, alone)
     for N, E in fitted.items():
         assert E <= tuned[N] and (E == tuned[N] or E in A.CANDIDATES)
-        assert E == 1 or (ref_max + A.tile_words(N, E)) * word + A.STATIC_LDS <= budget
+        assert E == 1 or (ref_max + A.tile_words(N, E, P[N])) * word + A.STATIC_LDS <= budget
         if E < tuned[N]:          # the largest candidate that fits
             bigger = min(c for c in A.CANDIDATES if c > E)
-            assert (ref_max + A.tile_words(N, bigger)) * word + A.STATIC_LDS > budget
+            assert (ref_max + A.tile_words(N, bigger, P[N])) * word + A.STATIC_LDS > budget
     assert A.fit_mixed(prec, {3: 8}) == {3: 8}
 
 
@@ -91,7 +92,8 @@ def test_lds_model_matches_library_limit(prec):
     word = 8 if prec == "fp64" else 4
     for N in range(1, 6):
         w = wl.config2(n=2, N=N)
-        fits = [E for E in range(1, 65) if (A.ref_words(N) + A.tile_words(N, E)) * word <= 160 * 1024]
+        fits = [E for E in range(1, 65)
+                if (A.ref_words(N) + A.tile_words(N, E, A.default_shape(N, prec)[1])) * word <= 160 * 1024]
         emax = max(fits)
         assert _init_status(lib, w, prec, emax) == binding.ESDG_OK, (N, emax)
         if emax < 64:
@@ -127,3 +129,23 @@ def test_lookup_shapes_defaults_without_entry():
         assert shp == {3: A.shape_code(c["rows"], c["parts"])}
     else:
         assert shp is None
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_mixed_degrees_take_default_shape(prec):
+    """A launch of several degrees uses the default tile shape and, per degree, the E timed
+    fastest with it (then fitted to the shared LDS); so do the split-bf16 mode and
+    matrix-core contractions on one degree."""
+    c = _cache()
+    sizes = [(2, 1 << 20), (3, 1 << 20), (4, 1 << 20)]
+    e, shp = A.lookup_shapes(prec, sizes)
+    assert shp is None
+    best = {}
+    for N in (2, 3, 4):
+        ent = next(c[f"{prec}:N{N}:{cls}"] for cls in ("L", "M", "S") if f"{prec}:N{N}:{cls}" in c)
+        t = ent["us_per_stage"]
+        best[N] = int(min(t, key=lambda k: t[k])) if "rows" in ent else ent["epb"]
+    assert e == A.fit_mixed(prec, best)
+    for N in (1, 2, 3, 4, 5):
+        assert A.lookup_shapes("bf16x3", [(N, 131072)])[1] is None
+        assert A.lookup_shapes(prec, [(N, 131072)], valu=False)[1] is None
