@@ -224,7 +224,7 @@ __device__ __forceinline__ void wadg_first(int ne, const Lds<real, N> &L, const 
     const real *Yc = Y + c * ne * Np + e * Np;
     const real *Vq = L.Vh + q * Np;
     real a = 0, b = 0;
-#pragma unroll 16
+#pragma unroll 32
     for (int j = 0; j + 1 < Np; j += 2) {
       a += Vq[j] * Yc[j];
       b += Vq[j + 1] * Yc[j + 1];
@@ -239,7 +239,7 @@ template <typename real, int N>
 __device__ __forceinline__ real wadg_second(const Lds<real, N> &L, const real *Sc, int row) {
   constexpr int Np = dim_Np(N), Nq = dim_Nq(N);
   real a = 0, b = 0;
-#pragma unroll 16
+#pragma unroll 32
   for (int q = 0; q + 1 < Nq; q += 2) {
     a += L.Vh[q * Np + row] * Sc[q];
     b += L.Vh[(q + 1) * Np + row] * Sc[q + 1];
@@ -286,7 +286,7 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
       u1 = Stage[(1 * ne + e) * Nq + q];
       u2 = Stage[(2 * ne + e) * Nq + q];
     } else {
-#pragma unroll 16
+#pragma unroll 32
       for (int j = 0; j < Np; ++j) {
         const real v = L.Vh[q * Np + j];
         u0 += v * L.U[0 * ne * Np + e * Np + j];
@@ -315,7 +315,7 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
     const int c = (i >= ne * Np) + (i >= 2 * ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
     const real *Qc = L.Q + c * ne * Nq + e * Nq;
     real ya = 0, yb = 0;
-#pragma unroll 16
+#pragma unroll 32
     for (int q = 0; q + 1 < Nq; q += 2) {
       ya += L.Vh[q * Np + j] * Qc[q];
       yb += L.Vh[(q + 1) * Np + j] * Qc[q + 1];
@@ -337,7 +337,7 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
       const real *Mi = L.Minv + (e * Np + row) * Np;
       const real *Tc = L.T + c * ne * Np + e * Np;
       real va = 0, vb = 0;
-#pragma unroll 16
+#pragma unroll 32
       for (int j = 0; j + 1 < Np; j += 2) {
         va += Mi[j] * Tc[j];
         vb += Mi[j + 1] * Tc[j + 1];
@@ -363,7 +363,7 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
       t1 = Stage[(1 * ne + e) * Nh + n];
       t2 = Stage[(2 * ne + e) * Nh + n];
     } else {
-#pragma unroll 16
+#pragma unroll 32
       for (int j = 0; j < Np; ++j) {
         const real v = L.Vh[n * Np + j];
         t0 += v * L.VH[0 * ne * Np + e * Np + j];
@@ -713,7 +713,7 @@ __device__ __forceinline__ void lift_valu(int ne, LT &L) {
     const int c = (i >= ne * Np) + (i >= 2 * ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
     const real *Rc = L.R + c * ne * Nh + e * Nh;
     real ya = 0, yb = 0;
-#pragma unroll 16
+#pragma unroll 32
     for (int n = 0; n < Nh; ++n) {
       real rn = Rc[n];
 #pragma unroll
@@ -918,7 +918,7 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
       const real *Mi = L.Minv + (e * Np + row) * Np;
       const real *Tc = L.T + c * ne * Np + e * Np;
       real ra0 = 0, ra1 = 0;
-#pragma unroll 16
+#pragma unroll 32
       for (int m = 0; m + 1 < Np; m += 2) {
         ra0 -= Mi[m] * Tc[m];
         ra1 -= Mi[m + 1] * Tc[m + 1];
