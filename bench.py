@@ -186,7 +186,7 @@ def host_cpu():
     return n, model
 
 
-def cpu_baseline(w, stages_pool=50, mass="stored", stages_single=25, max_workers=16):
+def cpu_baseline(w, stages_pool=200, mass="stored", stages_single=25, max_workers=16):
     """The FP64 oracle as it stands, timed on this host's cores: the RK stages of the same
     workload with each stage's right-hand side split into element chunks over a process
     pool (one worker per core, at most the host share of one GPU, 16; each worker calls the
