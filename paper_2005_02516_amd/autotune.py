@@ -67,7 +67,7 @@ def shape_code(R: int, P: int) -> int:
 
 def default_shape(N: int, precision: str) -> Tuple[int, int]:
     """The library's default (R, P)."""
-    return (2 if precision != "fp64" and N in (1, 3) else 1), (3 if precision != "fp64" and N == 5 else 2)
+    return (2 if precision != "fp64" and N in (1, 3) else 1), (1 if N == 5 else 2)
 
 
 def shapes(N: int, precision: str) -> List[Tuple[int, int]]:

@@ -8,6 +8,8 @@ namespace esdg {
 
 constexpr int kMaxN = 5;
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64s)
+constexpr int kBlockWide = 512;    // stage-kernel workgroups of launches whose kinds are all
+                                   // wide (wide_kind): 8 wave64s sharing one reference block
 constexpr int kNodeRec = 12;       // per hybrid node in LDS: hu/2 hv/2 u/2 v/2 | rxJ sxJ ryJ syJ | gh/2 dH h -
                                    // (three aligned quads, so a column is read with two 16-byte loads)
 constexpr int kXcds = 8;           // MI355X accelerator complex dies (each with its own L2)
@@ -90,6 +92,11 @@ constexpr int kShapeDefault = 0;
 __host__ __device__ constexpr int shape_rows(int shape) { return shape >> 4; }
 __host__ __device__ constexpr int shape_parts(int shape) { return shape & 15; }
 __host__ __device__ constexpr int make_shape(int R, int P) { return (R << 4) | P; }
+
+// Kinds with many hybrid nodes (N=5, and N=4 with N+2 points): their reference block fills
+// a quarter of a CU's LDS, so their launches run workgroups of kBlockWide threads (twice the
+// elements sharing one copy of it), and their residual rows use balanced column chunks.
+__host__ __device__ constexpr bool wide_kind(int D) { return !key_sbp(D) && dim_Nh(D) >= 50; }
 
 // Balanced column chunks of the residual phase (the kinds with many hybrid nodes; see
 // kernels.hip): volume rows (Nh columns) are cut into P chunks of residual_chunk columns

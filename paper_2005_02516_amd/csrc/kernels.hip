@@ -188,10 +188,11 @@ struct Lds {
 template <typename real, int N> struct RowsPerThread { static constexpr int value = 1; };
 template <> struct RowsPerThread<float, 1> { static constexpr int value = 2; };
 template <> struct RowsPerThread<float, 3> { static constexpr int value = 2; };
-// Default column chunks of the residual phase: three in float at N = 5 (whose volume rows
-// then split into chunks as long as the face rows' two), else two.
+// Default column chunks of the residual phase: one at N = 5 (whose 512-thread workgroups
+// have a task per row already), else two.
 template <typename real, int N> struct DefaultParts { static constexpr int value = 2; };
-template <> struct DefaultParts<float, 5> { static constexpr int value = 3; };
+template <> struct DefaultParts<float, 5> { static constexpr int value = 1; };
+template <> struct DefaultParts<double, 5> { static constexpr int value = 1; };
 
 // Tile shapes the residual phase is compiled for: R = 1 or 2 rows per thread (2 only in
 // float, where R divides Nq and Nfq: two rows of double accumulators exceed the register
@@ -455,7 +456,7 @@ constexpr int kCpolAgent = 16;     // sc1: device-coherent access (other XCDs' s
 // 32-bit words of a tile's static block staged through registers during a stage.
 template <typename real>
 __device__ __forceinline__ int stat_head(int nstat) {
-  constexpr int cap = StatRegs<real>::value * kBlock;
+  const int cap = StatRegs<real>::value * int(blockDim.x);
   return nstat < cap ? nstat : cap;
 }
 
@@ -488,7 +489,7 @@ __device__ __forceinline__ void fetch_tile(const StageArgs &a, const InstDesc &d
   }
   {
     // static block (mass data, w J, b, push targets): contiguous in HBM and in LDS.  A
-    // stage copies only the part beyond the first kStatRegs * kBlock words here; that head
+    // stage copies only the part beyond the first kStatRegs words per thread here; that head
     // goes through registers and lands in LDS after the residual (stage_tile).
     constexpr int SW = stat_words(N, WADG);
     const int nstat = ne * SW * W, head = a.mode == kProject ? 0 : stat_head<real>(nstat);
@@ -616,9 +617,8 @@ __device__ __forceinline__ void row_sums(const InstDesc &d, int ne, int e, int r
 // types into chunks of one length (residual_chunk), so that volume and face tasks sharing
 // a wave run about the same trip count through one loop; the chunk partials are then
 // summed once (sum_partials) instead of in every lift task.
-template <int D> __host__ __device__ constexpr bool wide_kind() { return dim_Nh(D) >= 50; }
 template <int D, int P> __host__ __device__ constexpr int face_chunks() {
-  return wide_kind<D>() ? residual_face_parts(D, P) : P;
+  return wide_kind(D) ? residual_face_parts(D, P) : P;
 }
 
 template <typename real, int N, int R, int P, class LT>
@@ -629,7 +629,7 @@ __device__ __forceinline__ void residual_tile(const InstDesc &d, int ne, LT &L, 
   const int tid = phase_tid(), nth = blockDim.x;
   const int nv = ne * VB * P, ntask = nv + ne * FB * PF;
   for (int t = tid; t < ntask; t += nth) {
-    if constexpr (wide_kind<N>()) {
+    if constexpr (wide_kind(N)) {
       constexpr int C = residual_chunk(N, P);
       const bool face = t >= nv;
       int p, e, b;
@@ -729,11 +729,11 @@ __device__ __forceinline__ void lift_valu(int ne, LT &L) {
 template <typename real, int N, int P, int CM, class LT>
 __device__ __forceinline__ void lift_partials(int ne, LT &L) {
   constexpr int Np = dim_Np(N), Nh = dim_Nh(N);
-  if constexpr (wide_kind<N>() && P > 1) {
+  if constexpr (wide_kind(N) && P > 1) {
     sum_partials<real, N, P>(ne, L);
     __syncthreads();
   }
-  constexpr int PS = wide_kind<N>() ? 1 : P;
+  constexpr int PS = wide_kind(N) ? 1 : P;
   if constexpr (CM != kValu) {
     gemm_mfma<CM, real>(Np, Nh, 3 * ne, [&](int i, int k) { return L.Vh[k * Np + i]; },
                         [&](int k, int c) {
@@ -837,7 +837,7 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
   if (a.mode != kProject && !mid) {
 #pragma unroll
     for (int j = 0; j < SR; ++j) {
-      const int v = tid + j * kBlock;
+      const int v = tid + j * nth;
       sreg[j] = v < head ? sg[v] : 0u;
     }
   }
@@ -866,7 +866,7 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
     uint32_t *sl = reinterpret_cast<uint32_t *>(L.Minv);
 #pragma unroll
     for (int j = 0; j < SR; ++j) {
-      const int v = tid + j * kBlock;
+      const int v = tid + j * nth;
       if (v < head) sl[v] = sreg[j];
     }
   } else {
@@ -964,7 +964,7 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
 // whose register allocation those larger kinds do not affect.  SHAPES: see stage_tile
 // (built with vector-ALU contractions and variant-0 kinds only).
 template <typename real, int CM, bool WADG, bool MULTI, bool V1, bool SHAPES>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kBlockWide) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel(StageArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   real *sm = reinterpret_cast<real *>(smem_raw);
@@ -1390,7 +1390,8 @@ static const void *sbp_fn(bool fp64) {
 
 // Workgroups of the stage kernel (the DG-SBP kernel with sbp) that stay resident on the
 // whole device.
-hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, bool sbp, bool v1, bool shapes, size_t lds_bytes, int *out) {
+hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, bool sbp, bool v1, bool shapes, size_t lds_bytes, int block,
+                            int *out) {
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -1409,7 +1410,7 @@ hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, bool sbp, bool v1, boo
   for (int multi = 0; multi < 2; ++multi) {
     const void *fn = sbp ? sbp_fn(fp64) : stage_fn(fp64, cm, wadg, multi != 0, v1, shapes);
     int n = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kBlock, lds_bytes);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, lds_bytes);
     if (e != hipSuccess) return e;
     hipFuncAttributes fa{};
     e = hipFuncGetAttributes(&fa, fn);
@@ -1440,23 +1441,25 @@ int stage_grid(int ntiles, int max_blocks) {
   return ((g + kXcds - 1) / kXcds) * kXcds;
 }
 
-hipError_t launch_stage(bool fp64, bool sbp, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream) {
+hipError_t launch_stage(bool fp64, bool sbp, const StageArgs &a, int max_blocks, size_t lds_bytes, int block,
+                        hipStream_t stream) {
   if (a.ntiles <= 0) return hipSuccess;
   const int grid = stage_grid(a.ntiles, max_blocks);
   StageArgs arg = a;
   void *params[] = {&arg};
   return hipLaunchKernel(sbp ? sbp_fn(fp64) : stage_fn(fp64, a.contraction, a.wadg != 0, false, a.v1 != 0, a.shapes != 0), dim3(grid),
-                         dim3(kBlock), params, lds_bytes, stream);
+                         dim3(sbp ? kBlock : block), params, lds_bytes, stream);
 }
 
 // Multi-stage launch: every workgroup of the grid must be resident at once (tiles wait on
 // their neighbours' progress), which the cooperative launch guarantees or refuses.
-hipError_t launch_stage_fused(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream) {
+hipError_t launch_stage_fused(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, int block,
+                              hipStream_t stream) {
   if (a.ntiles <= 0) return hipSuccess;
   const int grid = stage_grid(a.ntiles, max_blocks);
   StageArgs arg = a;
   void *params[] = {&arg};
-  return hipLaunchCooperativeKernel(stage_fn(fp64, a.contraction, a.wadg != 0, true, a.v1 != 0, a.shapes != 0), dim3(grid), dim3(kBlock), params,
+  return hipLaunchCooperativeKernel(stage_fn(fp64, a.contraction, a.wadg != 0, true, a.v1 != 0, a.shapes != 0), dim3(grid), dim3(block), params,
                                     lds_bytes, stream);
 }
 

@@ -20,9 +20,12 @@
 
 namespace esdg {
 hipError_t set_stage_lds_limit(bool fp64, int cm, bool wadg, bool sbp, bool v1, bool shapes, size_t lds_bytes);
-hipError_t launch_stage(bool fp64, bool sbp, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream);
-hipError_t launch_stage_fused(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, hipStream_t stream);
-hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, bool sbp, bool v1, bool shapes, size_t lds_bytes, int *out);
+hipError_t launch_stage(bool fp64, bool sbp, const StageArgs &a, int max_blocks, size_t lds_bytes, int block,
+                        hipStream_t stream);
+hipError_t launch_stage_fused(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, int block,
+                              hipStream_t stream);
+hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, bool sbp, bool v1, bool shapes, size_t lds_bytes, int block,
+                            int *out);
 int stage_grid(int ntiles, int max_blocks);
 hipError_t launch_diag(bool fp64, const DiagArgs &a, hipStream_t stream);
 hipError_t launch_rest_depth(bool fp64, const DiagArgs &a, hipStream_t stream);
@@ -83,27 +86,28 @@ size_t noalloc_bytes(int N, int K, size_t word) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Default elements per workgroup of an element kind: as many as keep E*Nh <= 512 and the
-// tile's LDS <= 40 KiB (with the reference block, several workgroups stay resident per CU).
-int default_epb(int D, size_t word, bool wadg, int P) {
+// Default elements per workgroup of an element kind: as many as keep E*Nh <= 2 per thread
+// and the tile's LDS <= 40 KiB per 256 threads (with the reference block, several
+// workgroups stay resident per CU).
+int default_epb(int D, size_t word, bool wadg, int P, int block) {
   int best = 1;
   for (int E = 1; E <= 64; E *= 2) {
-    if (E * dim_Nh(D) > 512) break;
-    if (size_t(tile_words(D, E, wadg, P)) * word > 40 * 1024) break;
+    if (E * dim_Nh(D) > 2 * block) break;
+    if (size_t(tile_words(D, E, wadg, P)) * word > size_t(40 * 1024) * block / kBlock) break;
     best = E;
   }
   return best;
 }
 
 // Default tile shape of the residual phase (kernels.hip: RowsPerThread, DefaultParts): two
-// rows per thread in float at N = 1 and 3 of the default quadrature, else one; three column
-// chunks in float at N = 5 of the default quadrature, else two.  (DG-SBP tiles use one row
-// and two chunks always.)
+// rows per thread in float at N = 1 and 3 of the default quadrature, else one; one column
+// chunk at N = 5 of the default quadrature, else two.  (DG-SBP tiles use one row and two
+// chunks always.)
 int default_shape(int D, bool fp64) {
-  const bool v0 = !fp64 && key_variant(D) == 0;
-  const bool two = v0 && (key_N(D) == 1 || key_N(D) == 3);
-  const bool three = v0 && key_N(D) == 5;
-  return make_shape(two ? 2 : 1, three ? 3 : 2);
+  const bool v0 = key_variant(D) == 0;
+  const bool two = v0 && !fp64 && (key_N(D) == 1 || key_N(D) == 3);
+  const bool one = v0 && key_N(D) == 5;
+  return make_shape(two ? 2 : 1, one ? 1 : 2);
 }
 
 // A tile shape the stage kernel is compiled for (kernels.hip: shape_ok).
@@ -146,6 +150,7 @@ struct esdg_swe {
   std::map<int, int> epb;          // elements per workgroup per element kind
   std::map<int, int> shape;        // tile shape of the residual phase per element kind
   size_t lds_bytes = 0;
+  int block = kBlock;              // stage-kernel workgroup size (kBlockWide if every kind is wide)
   int ref_max = 0;                 // LDS words reserved for the largest reference block
   int max_blocks = 0;              // resident workgroups of the stage kernel (set at bind)
   std::vector<Tile> tiles;
@@ -226,7 +231,7 @@ esdg_status upload(esdg_swe *s, size_t off, const void *src, size_t bytes) {
 }
 
 esdg_status launch(esdg_swe *s, const StageArgs &a, int /*ntiles*/) {
-  hipError_t e = launch_stage(s->fp64, s->sbp, a, s->max_blocks, s->lds_bytes, s->stream);
+  hipError_t e = launch_stage(s->fp64, s->sbp, a, s->max_blocks, s->lds_bytes, s->block, s->stream);
   if (e != hipSuccess) return s->hip_fail(e, "stage kernel launch");
   return ESDG_OK;
 }
@@ -475,6 +480,13 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
       return ESDG_EINVAL;
     }
   }
+  // workgroup size: kBlockWide when every kind is wide (its reference block is then shared
+  // by twice the elements), else kBlock
+  {
+    bool all_wide = !s->refs.empty();
+    for (auto &kv : s->refs) all_wide = all_wide && wide_kind(kv.first);
+    s->block = all_wide ? kBlockWide : kBlock;
+  }
   // elements per workgroup and LDS: the largest reference block + the largest tile
   size_t tile = 0;
   for (auto &kv : s->refs) {
@@ -489,7 +501,7 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
     s->shape[D] = shape;
     if (!s->sbp && shape != default_shape(D, s->fp64)) s->shapes = true;
     const int P = shape_parts(shape);
-    int E = opt->elems_per_block[N] ? opt->elems_per_block[N] : default_epb(D, s->word, s->wadg, P);
+    int E = opt->elems_per_block[N] ? opt->elems_per_block[N] : default_epb(D, s->word, s->wadg, P, s->block);
     s->epb[D] = E;
     s->ref_max = std::max(s->ref_max, ref_words(D));
     tile = std::max(tile, size_t(tile_words(D, E, s->wadg, P)));
@@ -591,13 +603,14 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
     if (e != hipSuccess) return s->hip_fail(e, "hipFuncSetAttribute (LDS)");
   }
   {
-    hipError_t e = stage_max_blocks(s->fp64, s->contraction, s->wadg, s->sbp, s->v1, s->shapes, s->lds_bytes,
+    hipError_t e = stage_max_blocks(s->fp64, s->contraction, s->wadg, s->sbp, s->v1, s->shapes, s->lds_bytes, s->block,
                                     &s->max_blocks);
     if (e != hipSuccess) return s->hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (std::getenv("ESDG_SWE_VERBOSE")) {
-      std::fprintf(stderr, "esdg_swe: %s, LDS %zu B per workgroup, %d resident workgroups, %zu tiles;",
+      std::fprintf(stderr, "esdg_swe: %s, %d threads and LDS %zu B per workgroup, %d resident workgroups, %zu tiles;",
                    s->fp64 ? (s->contraction ? "fp64+mfma" : "fp64")
-                           : (s->bf16x3 ? "fp32+bf16x3" : (s->contraction ? "fp32+mfma" : "fp32")), s->lds_bytes, s->max_blocks, s->tiles.size());
+                           : (s->bf16x3 ? "fp32+bf16x3" : (s->contraction ? "fp32+mfma" : "fp32")), s->block, s->lds_bytes,
+                   s->max_blocks, s->tiles.size());
       for (auto &kv : s->epb)
         std::fprintf(stderr, " N=%d%s: %d elements/tile", key_N(kv.first),
                      key_variant(kv.first) == 1 ? " (N+2 points)" : (key_sbp(kv.first) ? " (DG-SBP)" : ""), kv.second);
@@ -915,7 +928,7 @@ static esdg_status run_steps_fused(esdg_swe *s, int nsteps) {
       a.rk_a5[st] = kRkA[st];
       a.rk_b5[st] = kRkB[st];
     }
-    hipError_t e = launch_stage_fused(s->fp64, a, s->max_blocks, s->lds_bytes, s->stream);
+    hipError_t e = launch_stage_fused(s->fp64, a, s->max_blocks, s->lds_bytes, s->block, s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "hipLaunchCooperativeKernel (fused steps)");
     s->stage_count += 5LL * n;
     if (n & 1) s->parity = 1 - s->parity;
