@@ -47,12 +47,23 @@ __host__ __device__ constexpr int dim_Np(int D) { return key_sbp(D) ? dim_Nq(D) 
 __host__ __device__ constexpr int dim_Nfq(int D) { return 3 * dim_Nfp(D); }
 __host__ __device__ constexpr int dim_Nh(int D) { return dim_Nq(D) + dim_Nfq(D); }
 
-// Relative cost of one element of kind D in a stage (flux-differencing and contraction
-// flops), used to balance persistent workgroups over mixed-degree tile lists.
-__host__ __device__ constexpr long long elem_cost(int D) {
+// Operation count of one element of kind D in a stage: 35 FLOPs per unordered nonzero node
+// pair of the flux differencing, and the projection and lift contractions.
+__host__ __device__ constexpr long long elem_work(int D) {
   return 35LL * (dim_Nq(D) * (dim_Nq(D) - 1) / 2 + dim_Nq(D) * dim_Nfq(D)) +
          (key_sbp(D) ? 0LL
                      : 6LL * (2 * dim_Nq(D) * dim_Np(D) + 2 * dim_Np(D) * dim_Np(D) + 2 * dim_Nh(D) * dim_Np(D)));
+}
+
+// Relative cost of one element of kind D in a stage, for splitting the tiles of a
+// mixed-degree launch into ranges of equal cost.  The operation count overstates the higher
+// degrees (their phases keep more lanes busy), so the default-quadrature modal kinds take
+// measured per-element stage times instead: single-degree meshes of 131072 elements, FP32,
+// tuned tiles of 256-thread workgroups, relative to N=2 (0.87 ns) in hundredths; the other
+// kinds scale their degree's figure by their operation count relative to it.
+constexpr long long kStageCost[6] = {0, 46, 100, 182, 384, 724};
+__host__ __device__ constexpr long long elem_cost(int D) {
+  return kStageCost[key_N(D)] * elem_work(D) / elem_work(key_N(D));
 }
 
 // Reference-operator block of kind D, stored contiguously in the bulk precision:
