@@ -848,7 +848,9 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
                               MULTI && a.progress != nullptr);
     return true;
   }
-  __syncthreads();
+  // a resident tile after its first stage skips the fetch and the records: what its residual
+  // reads (the node records) was written before the barrier of the previous stage's publish
+  if (!mid) __syncthreads();
   // phase 1: node records from the fetched u~ and metric factors (a resident tile's
   // previous projection wrote them directly)
   for (int i = tid; i < ne * Nh && !mid; i += nth) {
@@ -859,7 +861,7 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
     rec[1] = real4{L.raw[4 * ne * Nh + i], L.raw[5 * ne * Nh + i], L.raw[6 * ne * Nh + i], L.raw[7 * ne * Nh + i]};
     rec[2] = real4{real(0.5) * g * h, dH, h, real(0)};
   }
-  __syncthreads();
+  if (!mid) __syncthreads();
   if constexpr (SHAPES) residual_shaped<real, N>(d, ne, L, !mid, shape);
   else residual_tile<real, N, RowsPerThread<real, N>::value, DefaultParts<real, N>::value>(d, ne, L, !mid);
   if (!mid) {
