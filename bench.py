@@ -5,8 +5,8 @@ Workload (N=3, the degree the metric is quoted at): periodic [0,2]^2, 64x64 squa
 into 8192 curved triangles (nodes warped by 0.05 sin(pi x) sin(pi y)), bathymetry
 b = 0.1 sin(pi x) cos(pi y) + 0.1, lake at rest H = 2.2 plus a seeded Gaussian bump of
 amplitude 0.01, Lax-Friedrichs interface flux, g = 1.  A step is one LSRK4(5) step (five
-RK stages); the library's automatic plan runs all stages of a step call in one cooperative
-launch when every tile gets a resident workgroup (this mesh in FP32), else one launch per
+RK stages); the library's automatic plan runs all stages of a step call in one launch of
+resident workgroups when every tile gets one (this mesh in FP32), else one launch per
 stage replayed from HIP graphs.  Inputs are resident in HBM before the timed region.
 value = K * Np / (time per RK stage), FP32 bulk path with FP64 entropy round trip; the
 FP64 path is timed on the same workload for the speedup.
@@ -65,8 +65,8 @@ def alg_bytes_per_elem(N, word, wadg=False):
 TRAFFIC_FILES = sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.txt")))
 FUSED_ARG = {"auto": "auto", "per-stage": False, "fused": True}
 STEP_MODES = {0: "one launch per RK stage (HIP graph replays)",
-              1: "one cooperative launch per step call, tiles re-read every stage",
-              2: "one cooperative launch per step call, tiles resident in LDS across stages"}
+              1: "one launch of resident workgroups per step call, tiles re-read every stage",
+              2: "one launch of resident workgroups per step call, tiles resident in LDS across stages"}
 
 
 def kernel_source_hash():
@@ -378,7 +378,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--launch", choices=["auto", "per-stage", "fused"], default="auto",
                     help="per-stage: one launch per RK stage (graph replays); fused: all stages of a step "
-                         "call in one cooperative launch with neighbour-tile waits; auto (default): fused "
+                         "call in one launch of resident workgroups with neighbour-tile waits; auto (default): fused "
                          "when every workgroup holds one tile, which then stays in LDS")
     ap.add_argument("--volume-ratio", action="store_true",
                     help="the Section 5.4 volume-kernel cost ratio (entropy-stable / traditional) instead")

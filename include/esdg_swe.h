@@ -164,7 +164,9 @@ typedef struct {
                                ESDG_FP32_BF16X3 always uses the split-bf16 matrix-core path  */
   int32_t fused_steps;      /* how esdg_swe_step launches its RK stages: 0 = one launch per
                                stage (HIP graphs if use_graph); 1 = all stages of the call in
-                               one cooperative launch, each element tile starting a stage once
+                               one launch whose workgroups are all resident (an ordinary
+                               launch if a probe at bind saw the grid resident, else a
+                               cooperative one), each element tile starting a stage once
                                the tiles of its face neighbours have finished the previous
                                one (no grid-wide barrier); when every workgroup holds at most
                                one tile, that tile also stays in LDS from the first stage to
@@ -202,7 +204,9 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
 
 /* Attach a caller-owned device workspace (>= workspace_bytes, 256-byte aligned) and a
  * HIP stream (hipStream_t as void*, NULL = default stream), then upload the operators
- * and mesh data with asynchronous copies on that stream.  The handle keeps both. */
+ * and mesh data with asynchronous copies on that stream.  The handle keeps both.  With
+ * fused_steps, bind also runs one residency probe of the multi-stage grid (every
+ * workgroup counts itself in and waits, bounded, for the rest) and synchronises. */
 esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *hip_stream);
 
 /* Set instance `inst`'s state from samples at its geometry nodes: u_nodes is host
@@ -249,8 +253,7 @@ esdg_status esdg_swe_rhs_noalloc(esdg_swe *s, int32_t inst, const void *state_de
 /* Advance every instance by nsteps LSRK4(5) steps (5 RHS evaluations each, Section 4).
  * dt is a host array with one time step per instance.  Asynchronous on the bound stream:
  * one kernel launch per RK stage for all instances together, replayed from HIP graphs
- * when use_graph is set, or one cooperative launch for all nsteps stages when fused_steps
- * is set.  Non-physical states (ESDG_ENONPHYS) and a fused launch whose neighbour wait
+ * when use_graph is set, or one launch for all nsteps stages when fused_steps is set.  Non-physical states (ESDG_ENONPHYS) and a fused launch whose neighbour wait
  * gave up (ESDG_EDEVICE; the state is then undefined) are reported by the next
  * synchronising call (get_state, diagnostics, sync). */
 esdg_status esdg_swe_step(esdg_swe *s, const double *dt, int32_t nsteps);

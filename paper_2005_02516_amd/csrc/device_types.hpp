@@ -12,6 +12,7 @@ constexpr int kBlockWide = 512;    // stage-kernel workgroups of launches whose 
                                    // wide (wide_kind): 8 wave64s sharing one reference block
 constexpr int kNodeRec = 12;       // per hybrid node in LDS: hu/2 hv/2 u/2 v/2 | rxJ sxJ ryJ syJ | gh/2 dH h -
                                    // (three aligned quads, so a column is read with two 16-byte loads)
+constexpr int kProbeWord = 16;     // int32 word of the flag block counting a residency probe
 constexpr int kXcds = 8;           // MI355X accelerator complex dies (each with its own L2)
 
 // Push-target flag: the face node lies on a reflective wall (Section 2.9); its projection
@@ -182,7 +183,8 @@ struct Tile {
 enum StageMode : int32_t {
   kProject = 0,   // state -> entropy-projected values (ut[out])
   kRhs = 1,       // ut[in] -> rhs (no update)
-  kStage = 2      // ut[in] -> rhs -> LSRK update of uh, du -> project new uh to ut[out]
+  kStage = 2,     // ut[in] -> rhs -> LSRK update of uh, du -> project new uh to ut[out]
+  kProbe = 3      // residency probe of a multi-stage grid (no tile work; see stage_kernel)
 };
 
 struct StageArgs {

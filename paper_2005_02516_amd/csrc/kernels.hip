@@ -965,9 +965,33 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
 // per face); launches whose instances are all of variant 0 use the build without them,
 // whose register allocation those larger kinds do not affect.  SHAPES: see stage_tile
 // (built with vector-ALU contractions and variant-0 kinds only).
+// Residency probe of a multi-stage grid (kProbe): every workgroup counts itself in and waits,
+// with a bounded spin, until the whole grid has; a wait that gives up sets flag bit 2.  Run
+// once at bind with the grid, workgroup size and LDS of the multi-stage launches: if every
+// workgroup was resident at once, those launches go out as ordinary launches, else as
+// cooperative ones.  The count is a word of the flag block of its own.
+__device__ __forceinline__ void residency_probe(const StageArgs &a) {
+  if (threadIdx.x == 0) {
+    int32_t *count = a.flag + kProbeWord;
+    __hip_atomic_fetch_add(count, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int spins = 0;
+    while (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < int(gridDim.x)) {
+      if (++spins > a.spin_limit) {
+        atomicOr(a.flag, 4);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+}
+
 template <typename real, int CM, bool WADG, bool MULTI, bool V1, bool SHAPES>
 __global__ void __launch_bounds__(kBlockWide) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel(StageArgs a) {
+  if (MULTI && a.mode == kProbe) {
+    residency_probe(a);
+    return;
+  }
   extern __shared__ __align__(16) unsigned char smem_raw[];
   real *sm = reinterpret_cast<real *>(smem_raw);
   real *tile = sm + a.ref_words_max;
@@ -1456,13 +1480,14 @@ hipError_t launch_stage(bool fp64, bool sbp, const StageArgs &a, int max_blocks,
 // Multi-stage launch: every workgroup of the grid must be resident at once (tiles wait on
 // their neighbours' progress), which the cooperative launch guarantees or refuses.
 hipError_t launch_stage_fused(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, int block,
-                              hipStream_t stream) {
+                              bool cooperative, hipStream_t stream) {
   if (a.ntiles <= 0) return hipSuccess;
   const int grid = stage_grid(a.ntiles, max_blocks);
   StageArgs arg = a;
   void *params[] = {&arg};
-  return hipLaunchCooperativeKernel(stage_fn(fp64, a.contraction, a.wadg != 0, true, a.v1 != 0, a.shapes != 0), dim3(grid), dim3(block), params,
-                                    lds_bytes, stream);
+  const void *fn = stage_fn(fp64, a.contraction, a.wadg != 0, true, a.v1 != 0, a.shapes != 0);
+  if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), params, lds_bytes, stream);
+  return hipLaunchKernel(fn, dim3(grid), dim3(block), params, lds_bytes, stream);
 }
 
 hipError_t launch_diag(bool fp64, const DiagArgs &a, hipStream_t stream) {

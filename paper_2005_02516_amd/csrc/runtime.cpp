@@ -23,7 +23,7 @@ hipError_t set_stage_lds_limit(bool fp64, int cm, bool wadg, bool sbp, bool v1, 
 hipError_t launch_stage(bool fp64, bool sbp, const StageArgs &a, int max_blocks, size_t lds_bytes, int block,
                         hipStream_t stream);
 hipError_t launch_stage_fused(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, int block,
-                              hipStream_t stream);
+                              bool cooperative, hipStream_t stream);
 hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, bool sbp, bool v1, bool shapes, size_t lds_bytes, int block,
                             int *out);
 int stage_grid(int ntiles, int max_blocks);
@@ -151,6 +151,8 @@ struct esdg_swe {
   std::map<int, int> shape;        // tile shape of the residual phase per element kind
   size_t lds_bytes = 0;
   int block = kBlock;              // stage-kernel workgroup size (kBlockWide if every kind is wide)
+  bool cooperative = true;         // multi-stage launches through hipLaunchCooperativeKernel (false
+                                   // once the residency probe at bind saw the whole grid resident)
   int ref_max = 0;                 // LDS words reserved for the largest reference block
   int max_blocks = 0;              // resident workgroups of the stage kernel (set at bind)
   std::vector<Tile> tiles;
@@ -763,6 +765,31 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
   if (e != hipSuccess) return s->hip_fail(e, "hipMemsetAsync (flag)");
   e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return s->hip_fail(e, "hipStreamSynchronize (bind)");
+  // Multi-stage launches need every workgroup of their grid resident at once.  The grid is
+  // what the occupancy query (capped by LDS granules) says fits, so an ordinary launch of it
+  // is normally resident, and it is cheaper than a cooperative one (about 5 % per stage at
+  // config 2).  A probe launch with the same grid, workgroup size and LDS checks that here;
+  // if any workgroup waited in vain the multi-stage launches stay cooperative.  (Their
+  // neighbour waits are bounded either way: a grid that is not resident makes step fail.)
+  s->cooperative = true;
+  if (s->fused) {
+    StageArgs a = base_args(s, -1);
+    a.mode = kProbe;
+    a.spin_limit = 1 << 17;
+    e = launch_stage_fused(s->fp64, a, s->max_blocks, s->lds_bytes, s->block, false, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return s->hip_fail(e, "residency probe");
+    int32_t word[2] = {0, 0};
+    e = hipMemcpy(&word[0], s->dev<int32_t>(s->flag_off), sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+      e = hipMemcpy(&word[1], s->dev<int32_t>(s->flag_off) + kProbeWord, sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return s->hip_fail(e, "hipMemcpy (residency probe)");
+    s->cooperative = (word[0] & 4) != 0 || word[1] != stage_grid(int(s->tiles.size()), s->max_blocks);
+    e = hipMemset(s->ws + s->flag_off, 0, 256);
+    if (e != hipSuccess) return s->hip_fail(e, "hipMemset (flag)");
+    if (std::getenv("ESDG_SWE_VERBOSE"))
+      std::fprintf(stderr, "esdg_swe: multi-stage launches %s\n", s->cooperative ? "cooperative" : "ordinary");
+  }
   s->bound = true;
   return ESDG_OK;
 }
@@ -928,7 +955,7 @@ static esdg_status run_steps_fused(esdg_swe *s, int nsteps) {
       a.rk_a5[st] = kRkA[st];
       a.rk_b5[st] = kRkB[st];
     }
-    hipError_t e = launch_stage_fused(s->fp64, a, s->max_blocks, s->lds_bytes, s->block, s->stream);
+    hipError_t e = launch_stage_fused(s->fp64, a, s->max_blocks, s->lds_bytes, s->block, s->cooperative, s->stream);
     if (e != hipSuccess) return s->hip_fail(e, "hipLaunchCooperativeKernel (fused steps)");
     s->stage_count += 5LL * n;
     if (n & 1) s->parity = 1 - s->parity;
