@@ -198,7 +198,8 @@ struct StageArgs {
   int32_t wadg;           // 0: stored inverse mass matrices; 1: weight-adjusted inverse
   int32_t v1;             // an instance is of a variant-1 kind (selects the stage-kernel build)
   int32_t shapes;         // an instance's tile shape is not the default (selects the build)
-  int32_t pad_s;
+  int32_t kind;           // the element kind of every instance of a single-kind launch, which
+                          // then runs the kernel built for that kind alone; 0 otherwise
   const int32_t *ranges;  // optional [grid+1]: tile range of each block's chunk (cost-balanced);
                           // null means equal numbers of tiles per chunk
   int32_t in_buf, out_buf;

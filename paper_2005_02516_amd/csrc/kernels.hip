@@ -964,7 +964,10 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
 // V1: the build that also holds the variant-1 element kinds (N+2 points per direction and
 // per face); launches whose instances are all of variant 0 use the build without them,
 // whose register allocation those larger kinds do not affect.  SHAPES: see stage_tile
-// (built with vector-ALU contractions and variant-0 kinds only).
+// (built with vector-ALU contractions and variant-0 kinds only).  KIND: a build for one
+// variant-0 kind alone (vector-ALU contractions, default shapes), used when every instance
+// is of that kind: its registers are allocated for that kind's code only (FP32 N=3: 95
+// VGPRs and 86 scalar spills against 122 and 105 for the build of all kinds).
 // Residency probe of a multi-stage grid (kProbe): every workgroup counts itself in and waits,
 // with a bounded spin, until the whole grid has; a wait that gives up sets flag bit 2.  Run
 // once at bind with the grid, workgroup size and LDS of the multi-stage launches: if every
@@ -985,7 +988,7 @@ __device__ __forceinline__ void residency_probe(const StageArgs &a) {
   }
 }
 
-template <typename real, int CM, bool WADG, bool MULTI, bool V1, bool SHAPES>
+template <typename real, int CM, bool WADG, bool MULTI, bool V1, bool SHAPES, int KIND = 0>
 __global__ void __launch_bounds__(kBlockWide) __attribute__((amdgpu_waves_per_eu(4)))
 stage_kernel(StageArgs a) {
   if (MULTI && a.mode == kProbe) {
@@ -1036,7 +1039,12 @@ stage_kernel(StageArgs a) {
       bool ok = true;
 #define ESDG_STAGE_CASE(D) \
   case D: ok = stage_tile<real, D, CM, WADG, MULTI, SHAPES>(as, d, tl.k0, tl.ne, sm, tile, res, t, a.stage0 + s); break;
-      if constexpr (V1) {
+      if constexpr (KIND != 0) {     // every tile is of this kind (the host's choice of kernel)
+        switch (d.N) {
+          ESDG_STAGE_CASE(KIND)
+          default: break;
+        }
+      } else if constexpr (V1) {
         switch (d.N) {
           ESDG_STAGE_CASE(1) ESDG_STAGE_CASE(2) ESDG_STAGE_CASE(3) ESDG_STAGE_CASE(4) ESDG_STAGE_CASE(5)
           ESDG_STAGE_CASE(9) ESDG_STAGE_CASE(10) ESDG_STAGE_CASE(11) ESDG_STAGE_CASE(12) ESDG_STAGE_CASE(13)
@@ -1356,10 +1364,10 @@ sbp_stage_kernel(StageArgs a) {
 // its combination by contraction mode and launch kind.
 #define ESDG_CAT4(a, b, c, d) a##b##c##d
 #define ESDG_UNIT_FN(R, W) ESDG_CAT4(stage_fn_unit_, R, _, W)
-const void *stage_fn_unit_float_0(int cm, bool multi, bool v1, bool shapes);
-const void *stage_fn_unit_float_1(int cm, bool multi, bool v1, bool shapes);
-const void *stage_fn_unit_double_0(int cm, bool multi, bool v1, bool shapes);
-const void *stage_fn_unit_double_1(int cm, bool multi, bool v1, bool shapes);
+const void *stage_fn_unit_float_0(int cm, bool multi, bool v1, bool shapes, int kind);
+const void *stage_fn_unit_float_1(int cm, bool multi, bool v1, bool shapes, int kind);
+const void *stage_fn_unit_double_0(int cm, bool multi, bool v1, bool shapes, int kind);
+const void *stage_fn_unit_double_1(int cm, bool multi, bool v1, bool shapes, int kind);
 
 #if defined(ESDG_UNIT_REAL)
 template <bool V1>
@@ -1383,9 +1391,28 @@ static const void *unit_fn(int cm, bool multi) {
                  : reinterpret_cast<const void *>(&stage_kernel<float, kValu, W, false, V1, false>);
   }
 }
-const void *ESDG_UNIT_FN(ESDG_UNIT_REAL, ESDG_UNIT_WADG)(int cm, bool multi, bool v1, bool shapes) {
+template <bool MULTI>
+static const void *kind_fn(int kind) {
   using real = ESDG_UNIT_REAL;
   constexpr bool W = ESDG_UNIT_WADG != 0;
+  switch (kind) {
+    case 1: return reinterpret_cast<const void *>(&stage_kernel<real, kValu, W, MULTI, false, false, 1>);
+    case 2: return reinterpret_cast<const void *>(&stage_kernel<real, kValu, W, MULTI, false, false, 2>);
+    case 3: return reinterpret_cast<const void *>(&stage_kernel<real, kValu, W, MULTI, false, false, 3>);
+    case 4: return reinterpret_cast<const void *>(&stage_kernel<real, kValu, W, MULTI, false, false, 4>);
+    case 5: return reinterpret_cast<const void *>(&stage_kernel<real, kValu, W, MULTI, false, false, 5>);
+    default: return nullptr;
+  }
+}
+const void *ESDG_UNIT_FN(ESDG_UNIT_REAL, ESDG_UNIT_WADG)(int cm, bool multi, bool v1, bool shapes, int kind) {
+  using real = ESDG_UNIT_REAL;
+  constexpr bool W = ESDG_UNIT_WADG != 0;
+  // one variant-0 kind, vector-ALU contractions and its default shape: that kind's own build
+  // (float launches of one stage run the multi-stage build, so float has no per-stage one)
+  if (kind >= 1 && kind <= 5 && cm == kValu && !v1 && !shapes) {
+    if (multi) return kind_fn<true>(kind);
+    if constexpr (std::is_same<real, double>::value) return kind_fn<false>(kind);
+  }
   if (shapes)                      // vector-ALU contractions, variant-0 kinds
     return multi ? reinterpret_cast<const void *>(&stage_kernel<real, kValu, W, true, false, true>)
                  : reinterpret_cast<const void *>(&stage_kernel<real, kValu, W, false, false, true>);
@@ -1403,10 +1430,11 @@ const void *ESDG_UNIT_FN(ESDG_UNIT_REAL, ESDG_UNIT_WADG)(int cm, bool multi, boo
 // progress counts) was measured faster on balance (same box: N=4 1.4 %, N=5 5 %, the
 // mixed-degree ensemble 11 %; the per-stage build is faster only at N=3, by 8 %), while
 // the per-stage build is 7-11 % faster in FP64 and 6 % with split-bf16 contractions.
-static const void *stage_fn(bool fp64, int cm, bool wadg, bool multi, bool v1, bool shapes) {
+static const void *stage_fn(bool fp64, int cm, bool wadg, bool multi, bool v1, bool shapes, int kind) {
   if (!fp64 && cm == kValu) multi = true;
-  if (fp64) return wadg ? stage_fn_unit_double_1(cm, multi, v1, shapes) : stage_fn_unit_double_0(cm, multi, v1, shapes);
-  return wadg ? stage_fn_unit_float_1(cm, multi, v1, shapes) : stage_fn_unit_float_0(cm, multi, v1, shapes);
+  if (fp64)
+    return wadg ? stage_fn_unit_double_1(cm, multi, v1, shapes, kind) : stage_fn_unit_double_0(cm, multi, v1, shapes, kind);
+  return wadg ? stage_fn_unit_float_1(cm, multi, v1, shapes, kind) : stage_fn_unit_float_0(cm, multi, v1, shapes, kind);
 }
 
 static const void *sbp_fn(bool fp64) {
@@ -1416,8 +1444,8 @@ static const void *sbp_fn(bool fp64) {
 
 // Workgroups of the stage kernel (the DG-SBP kernel with sbp) that stay resident on the
 // whole device.
-hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, bool sbp, bool v1, bool shapes, size_t lds_bytes, int block,
-                            int *out) {
+hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, bool sbp, bool v1, bool shapes, int kind, size_t lds_bytes,
+                            int block, int *out) {
   int dev = 0, ncu = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -1434,7 +1462,7 @@ hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, bool sbp, bool v1, boo
   e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
   if (e != hipSuccess) return e;
   for (int multi = 0; multi < 2; ++multi) {
-    const void *fn = sbp ? sbp_fn(fp64) : stage_fn(fp64, cm, wadg, multi != 0, v1, shapes);
+    const void *fn = sbp ? sbp_fn(fp64) : stage_fn(fp64, cm, wadg, multi != 0, v1, shapes, kind);
     int n = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, lds_bytes);
     if (e != hipSuccess) return e;
@@ -1450,12 +1478,13 @@ hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, bool sbp, bool v1, boo
   return hipSuccess;
 }
 
-hipError_t set_stage_lds_limit(bool fp64, int cm, bool wadg, bool sbp, bool v1, bool shapes, size_t lds_bytes) {
+hipError_t set_stage_lds_limit(bool fp64, int cm, bool wadg, bool sbp, bool v1, bool shapes, int kind,
+                               size_t lds_bytes) {
   if (sbp) return hipFuncSetAttribute(sbp_fn(fp64), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
-  hipError_t e = hipFuncSetAttribute(stage_fn(fp64, cm, wadg, false, v1, shapes), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    int(lds_bytes));
+  hipError_t e = hipFuncSetAttribute(stage_fn(fp64, cm, wadg, false, v1, shapes, kind),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_bytes));
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(stage_fn(fp64, cm, wadg, true, v1, shapes), hipFuncAttributeMaxDynamicSharedMemorySize,
+  return hipFuncSetAttribute(stage_fn(fp64, cm, wadg, true, v1, shapes, kind), hipFuncAttributeMaxDynamicSharedMemorySize,
                              int(lds_bytes));
 }
 
@@ -1473,7 +1502,8 @@ hipError_t launch_stage(bool fp64, bool sbp, const StageArgs &a, int max_blocks,
   const int grid = stage_grid(a.ntiles, max_blocks);
   StageArgs arg = a;
   void *params[] = {&arg};
-  return hipLaunchKernel(sbp ? sbp_fn(fp64) : stage_fn(fp64, a.contraction, a.wadg != 0, false, a.v1 != 0, a.shapes != 0), dim3(grid),
+  return hipLaunchKernel(sbp ? sbp_fn(fp64) : stage_fn(fp64, a.contraction, a.wadg != 0, false, a.v1 != 0, a.shapes != 0, a.kind),
+                         dim3(grid),
                          dim3(sbp ? kBlock : block), params, lds_bytes, stream);
 }
 
@@ -1485,7 +1515,7 @@ hipError_t launch_stage_fused(bool fp64, const StageArgs &a, int max_blocks, siz
   const int grid = stage_grid(a.ntiles, max_blocks);
   StageArgs arg = a;
   void *params[] = {&arg};
-  const void *fn = stage_fn(fp64, a.contraction, a.wadg != 0, true, a.v1 != 0, a.shapes != 0);
+  const void *fn = stage_fn(fp64, a.contraction, a.wadg != 0, true, a.v1 != 0, a.shapes != 0, a.kind);
   if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), params, lds_bytes, stream);
   return hipLaunchKernel(fn, dim3(grid), dim3(block), params, lds_bytes, stream);
 }

@@ -19,13 +19,14 @@
 #include "host_setup.hpp"
 
 namespace esdg {
-hipError_t set_stage_lds_limit(bool fp64, int cm, bool wadg, bool sbp, bool v1, bool shapes, size_t lds_bytes);
+hipError_t set_stage_lds_limit(bool fp64, int cm, bool wadg, bool sbp, bool v1, bool shapes, int kind,
+                               size_t lds_bytes);
 hipError_t launch_stage(bool fp64, bool sbp, const StageArgs &a, int max_blocks, size_t lds_bytes, int block,
                         hipStream_t stream);
 hipError_t launch_stage_fused(bool fp64, const StageArgs &a, int max_blocks, size_t lds_bytes, int block,
                               bool cooperative, hipStream_t stream);
-hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, bool sbp, bool v1, bool shapes, size_t lds_bytes, int block,
-                            int *out);
+hipError_t stage_max_blocks(bool fp64, int cm, bool wadg, bool sbp, bool v1, bool shapes, int kind, size_t lds_bytes,
+                            int block, int *out);
 int stage_grid(int ntiles, int max_blocks);
 hipError_t launch_diag(bool fp64, const DiagArgs &a, hipStream_t stream);
 hipError_t launch_rest_depth(bool fp64, const DiagArgs &a, hipStream_t stream);
@@ -151,6 +152,7 @@ struct esdg_swe {
   std::map<int, int> shape;        // tile shape of the residual phase per element kind
   size_t lds_bytes = 0;
   int block = kBlock;              // stage-kernel workgroup size (kBlockWide if every kind is wide)
+  int kind = 0;                    // the one element kind of every instance (modal), else 0
   bool cooperative = true;         // multi-stage launches through hipLaunchCooperativeKernel (false
                                    // once the residency probe at bind saw the whole grid resident)
   int ref_max = 0;                 // LDS words reserved for the largest reference block
@@ -255,6 +257,7 @@ StageArgs base_args(esdg_swe *s, int inst) {
   a.wadg = s->wadg ? 1 : 0;
   a.v1 = s->v1 ? 1 : 0;
   a.shapes = s->shapes ? 1 : 0;
+  a.kind = s->kind;
   return a;
 }
 
@@ -482,6 +485,8 @@ esdg_status esdg_swe_init(int32_t n_inst, const esdg_swe_instance *inst, const e
       return ESDG_EINVAL;
     }
   }
+  // one modal kind for every instance: the stage kernel built for that kind alone
+  if (s->refs.size() == 1 && !s->sbp) s->kind = s->refs.begin()->first;
   // workgroup size: kBlockWide when every kind is wide (its reference block is then shared
   // by twice the elements), else kBlock
   {
@@ -601,11 +606,11 @@ esdg_status esdg_swe_bind(esdg_swe *s, void *dev_workspace, size_t bytes, void *
     if (e != hipSuccess) return s->hip_fail(e, "hipGetSymbolAddress (scratch)");
   }
   if (s->lds_bytes > 64 * 1024) {
-    hipError_t e = set_stage_lds_limit(s->fp64, s->contraction, s->wadg, s->sbp, s->v1, s->shapes, s->lds_bytes);
+    hipError_t e = set_stage_lds_limit(s->fp64, s->contraction, s->wadg, s->sbp, s->v1, s->shapes, s->kind, s->lds_bytes);
     if (e != hipSuccess) return s->hip_fail(e, "hipFuncSetAttribute (LDS)");
   }
   {
-    hipError_t e = stage_max_blocks(s->fp64, s->contraction, s->wadg, s->sbp, s->v1, s->shapes, s->lds_bytes, s->block,
+    hipError_t e = stage_max_blocks(s->fp64, s->contraction, s->wadg, s->sbp, s->v1, s->shapes, s->kind, s->lds_bytes, s->block,
                                     &s->max_blocks);
     if (e != hipSuccess) return s->hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (std::getenv("ESDG_SWE_VERBOSE")) {
