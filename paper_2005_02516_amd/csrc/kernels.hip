@@ -55,6 +55,21 @@ __device__ __forceinline__ int phase_tid() {
   return t;
 }
 
+// Task i of a phase over (field c, element e, mode or node j) in [3][ne][M] order: c, the
+// offset r = e M + j within field c's block, e and j.  The products take 24-bit multiplies
+// and the division is unsigned by the constant M: 32-bit multiplies issue at a quarter of
+// the vector-ALU rate, and these phases run their index arithmetic once per task.
+template <int M>
+struct FieldTask {
+  int c, r, e, j;
+  __device__ __forceinline__ FieldTask(int i, int nem) {     // nem = ne * M
+    c = (i >= nem) + (i >= 2 * nem);
+    r = i - __umul24(unsigned(c), unsigned(nem));
+    e = int(unsigned(r) / unsigned(M));
+    j = r - __umul24(unsigned(e), unsigned(M));
+  }
+};
+
 // ---------------------------------------------------------------- matrix-core contractions
 // C[M x NC] = A[M x KD] B[KD x NC], A and B read from LDS, on the matrix cores.  One wave
 // per 16x16 output block; blocks are dealt to the workgroup's waves.  Lane layout of the
@@ -280,19 +295,21 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
     }
   }
   for (int i = tid; i < ne * Nq; i += nth) {
-    const int e = i / Nq, q = i - e * Nq;
+    const int e = int(unsigned(i) / unsigned(Nq)), q = i - __umul24(unsigned(e), unsigned(Nq));
     real u0 = 0, u1 = 0, u2 = 0;
     if (mfma) {
-      u0 = Stage[(0 * ne + e) * Nq + q];
-      u1 = Stage[(1 * ne + e) * Nq + q];
-      u2 = Stage[(2 * ne + e) * Nq + q];
+      u0 = Stage[i];
+      u1 = Stage[ne * Nq + i];
+      u2 = Stage[2 * ne * Nq + i];
     } else {
+      const real *Vq = L.Vh + __umul24(unsigned(q), unsigned(Np));
+      const real *Ue = L.U + __umul24(unsigned(e), unsigned(Np));
 #pragma unroll 32
       for (int j = 0; j < Np; ++j) {
-        const real v = L.Vh[q * Np + j];
-        u0 += v * L.U[0 * ne * Np + e * Np + j];
-        u1 += v * L.U[1 * ne * Np + e * Np + j];
-        u2 += v * L.U[2 * ne * Np + e * Np + j];
+        const real v = Vq[j];
+        u0 += v * Ue[j];
+        u1 += v * Ue[ne * Np + j];
+        u2 += v * Ue[2 * ne * Np + j];
       }
     }
     const double eta = u0, hu = u1, hv = u2;
@@ -313,15 +330,16 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
                   [&](int i, int c, real v) { L.T[c * Np + i] = v; });
   }
   for (int i = tid; i < 3 * ne * Np && !mfma; i += nth) {
-    const int c = (i >= ne * Np) + (i >= 2 * ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
-    const real *Qc = L.Q + c * ne * Nq + e * Nq;
+    const FieldTask<Np> k(i, ne * Np);
+    const real *Qc = L.Q + __umul24(unsigned(k.c), unsigned(ne * Nq)) + __umul24(unsigned(k.e), unsigned(Nq));
+    const real *Vj = L.Vh + k.j;
     real ya = 0, yb = 0;
 #pragma unroll 32
     for (int q = 0; q + 1 < Nq; q += 2) {
-      ya += L.Vh[q * Np + j] * Qc[q];
-      yb += L.Vh[(q + 1) * Np + j] * Qc[q + 1];
+      ya += Vj[q * Np] * Qc[q];
+      yb += Vj[(q + 1) * Np] * Qc[q + 1];
     }
-    if (Nq & 1) ya += L.Vh[(Nq - 1) * Np + j] * Qc[Nq - 1];
+    if (Nq & 1) ya += Vj[(Nq - 1) * Np] * Qc[Nq - 1];
     L.T[i] = ya + yb;
   }
   __syncthreads();
@@ -331,12 +349,13 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
     __syncthreads();
   }
   for (int i = tid; i < 3 * ne * Np; i += nth) {
-    const int c = (i >= ne * Np) + (i >= 2 * ne * Np), r = i - c * ne * Np, e = r / Np, row = r - e * Np;
+    const FieldTask<Np> k(i, ne * Np);
     if constexpr (WADG) {
-      L.VH[i] = wadg_second<real, N>(L, L.Q + c * ne * Nq + e * Nq, row);
+      L.VH[i] = wadg_second<real, N>(L, L.Q + __umul24(unsigned(k.c), unsigned(ne * Nq)) +
+                                            __umul24(unsigned(k.e), unsigned(Nq)), k.j);
     } else {
-      const real *Mi = L.Minv + (e * Np + row) * Np;
-      const real *Tc = L.T + c * ne * Np + e * Np;
+      const real *Mi = L.Minv + __umul24(unsigned(k.r), unsigned(Np));   // row (e, j) of Minv_e
+      const real *Tc = L.T + (i - k.j);                                  // T[c][e][0..Np)
       real va = 0, vb = 0;
 #pragma unroll 32
       for (int j = 0; j + 1 < Np; j += 2) {
@@ -357,19 +376,21 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
     }
   }
   for (int i = tid; i < ne * Nh; i += nth) {
-    const int e = i / Nh, n = i - e * Nh;
+    const int e = int(unsigned(i) / unsigned(Nh)), n = i - __umul24(unsigned(e), unsigned(Nh));
     real t0 = 0, t1 = 0, t2 = 0;
     if (mfma) {
-      t0 = Stage[(0 * ne + e) * Nh + n];
-      t1 = Stage[(1 * ne + e) * Nh + n];
-      t2 = Stage[(2 * ne + e) * Nh + n];
+      t0 = Stage[i];
+      t1 = Stage[ne * Nh + i];
+      t2 = Stage[2 * ne * Nh + i];
     } else {
+      const real *Vn = L.Vh + __umul24(unsigned(n), unsigned(Np));
+      const real *Ve = L.VH + __umul24(unsigned(e), unsigned(Np));
 #pragma unroll 32
       for (int j = 0; j < Np; ++j) {
-        const real v = L.Vh[n * Np + j];
-        t0 += v * L.VH[0 * ne * Np + e * Np + j];
-        t1 += v * L.VH[1 * ne * Np + e * Np + j];
-        t2 += v * L.VH[2 * ne * Np + e * Np + j];
+        const real v = Vn[j];
+        t0 += v * Ve[j];
+        t1 += v * Ve[ne * Np + j];
+        t2 += v * Ve[2 * ne * Np + j];
       }
     }
     const double v1 = t0, v2 = t1, v3 = t2;
@@ -382,15 +403,15 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
       rec[0] = real4{real(0.5) * hr * ur, real(0.5) * hr * vr, real(0.5) * ur, real(0.5) * vr};
       rec[2] = real4{real(0.5) * gr * hr, real(dH), hr, real(0)};
     } else {
-      const size_t o = size_t(k0) * 4 * Nh + i;   // tile-blocked [4][ne][Nh]
-      out[o] = real(h);
-      out[ne * Nh + o] = real(v2);
-      out[2 * ne * Nh + o] = real(v3);
-      out[3 * ne * Nh + o] = real(dH);
+      real *ot = out + size_t(k0) * 4 * Nh + unsigned(i);   // tile-blocked [4][ne][Nh]
+      ot[0] = real(h);
+      ot[ne * Nh] = real(v2);
+      ot[2 * ne * Nh] = real(v3);
+      ot[3 * ne * Nh] = real(dH);
     }
     if (n >= Nq) {                 // face node: also fill the neighbour's face slot
       const int f = n - Nq;
-      const uint32_t tgt = uint32_t(L.pp[e * Nfq + f]);
+      const uint32_t tgt = uint32_t(L.pp[__umul24(unsigned(e), unsigned(Nfq)) + f]);
       real *slot = nbx_out + size_t(tgt & ~kPushWall) * 4;
       double pu = v2, pv = v3;     // the velocity the exterior side of the face sees
       if (tgt & kPushWall) {
@@ -398,7 +419,7 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
         // normal velocity reversed, u+ = u - 2 (u . nJ) nJ / |nJ|^2, h+ = h (so H+ = H),
         // written into this node's own slot; nJ from the metric factors (tile-blocked, as
         // fetched) and the reference normal of the face
-        const real *gm = static_cast<const real *>(d.geo) + size_t(k0) * 4 * Nh + i;
+        const real *gm = static_cast<const real *>(d.geo) + size_t(k0) * 4 * Nh + unsigned(i);
         const double nr = double(L.nr[f]), ns = double(L.ns[f]);
         const double nx = double(gm[0]) * nr + double(gm[ne * Nh]) * ns;
         const double ny = double(gm[2 * ne * Nh]) * nr + double(gm[3 * ne * Nh]) * ns;
@@ -555,7 +576,7 @@ __device__ __forceinline__ void row_sums(const InstDesc &d, int ne, int e, int r
                                          int n_lo, int n_hi, const real *Stab, LD ld2, LT &L, bool iface) {
   constexpr int Nfq = dim_Nfq(N), Nh = dim_Nh(N);
   typedef real real4 __attribute__((ext_vector_type(4)));
-  const real *rbase = L.rec + e * Nh * kNodeRec;
+  const real *rbase = L.rec + __umul24(unsigned(e), unsigned(Nh * kNodeRec));
   real hu[R], hv[R], u[R], v[R], gh[R], rx[R], sx[R], ry[R], sy[R], a0[R], a1[R], a2[R];
   real b1[R], b2[R], q1[R], q2[R];
 #pragma unroll
@@ -598,16 +619,17 @@ __device__ __forceinline__ void row_sums(const InstDesc &d, int ne, int e, int r
     if (face && p == 0 && iface) {         // interface terms of face row m (else a later pass)
       const int f = r0 + r;
       real t0, t1, t2;
-      interface_terms<real>(rbase + m * kNodeRec, L.nb + (e * Nfq + f) * 4, L.wf[f], L.nr[f], L.ns[f], real(d.g),
-                            d.flux, t0, t1, t2);
+      interface_terms<real>(rbase + m * kNodeRec, L.nb + __umul24(unsigned(e), unsigned(Nfq * 4)) + f * 4, L.wf[f],
+                            L.nr[f], L.ns[f], real(d.g), d.flux, t0, t1, t2);
       a0[r] = a0[r] + t0;
       a1[r] = a1[r] + t1;
       a2[r] = a2[r] + t2;
     }
-    real *Rp = L.R + p * 3 * ne * Nh;     // partial sums of column chunk p
-    Rp[0 * ne * Nh + e * Nh + m] = a0[r];
-    Rp[1 * ne * Nh + e * Nh + m] = a1[r];
-    Rp[2 * ne * Nh + e * Nh + m] = a2[r];
+    // partial sums of column chunk p
+    real *Rp = L.R + __umul24(unsigned(p), unsigned(3 * ne * Nh)) + __umul24(unsigned(e), unsigned(Nh)) + m;
+    Rp[0] = a0[r];
+    Rp[ne * Nh] = a1[r];
+    Rp[2 * ne * Nh] = a2[r];
   }
 }
 
@@ -628,35 +650,37 @@ __device__ __forceinline__ void residual_tile(const InstDesc &d, int ne, LT &L, 
   static_assert(Nq % R == 0 && Nfq % R == 0, "R must divide Nq and Nfq");
   const int tid = phase_tid(), nth = blockDim.x;
   const int nv = ne * VB * P, ntask = nv + ne * FB * PF;
+  // task splits in unsigned arithmetic by constants (see FieldTask)
+  auto split = [](int t, unsigned parts, unsigned rows, int &p, int &e, int &b) {
+    const unsigned rest = unsigned(t) / parts;
+    p = t - __umul24(rest, parts);
+    e = int(rest / rows);
+    b = int(rest) - __umul24(unsigned(e), rows);
+  };
   for (int t = tid; t < ntask; t += nth) {
     if constexpr (wide_kind(N)) {
       constexpr int C = residual_chunk(N, P);
       const bool face = t >= nv;
       int p, e, b;
-      if (face) {
-        const int tt = t - nv, rest = tt / PF;
-        p = tt - rest * PF;
-        e = rest / FB;
-        b = rest - e * FB;
-      } else {
-        const int rest = t / P;
-        p = t - rest * P;
-        e = rest / VB;
-        b = rest - e * VB;
-      }
-      const int ncol = face ? Nq : Nh, n_lo = p * C, n_hi = n_lo + C < ncol ? n_lo + C : ncol;
+      if (face) split(t - nv, PF, FB, p, e, b);
+      else split(t, P, VB, p, e, b);
+      const int ncol = face ? Nq : Nh, n_lo = __umul24(unsigned(p), unsigned(C)),
+                n_hi = n_lo + C < ncol ? n_lo + C : ncol;
       const int r0 = b * R;
       row_sums<real, N, R>(d, ne, e, r0, face ? Nq + r0 : r0, p, face, n_lo, n_hi,
                            (face ? L.FT : L.ST) + 2 * r0, face ? 2 * Nfq : 2 * Nq, L, iface);
     } else {
+      int p, e, b;
       if (t < nv) {
-        const int p = t % P, rest = t / P, e = rest / VB, r0 = (rest - e * VB) * R;
-        row_sums<real, N, R>(d, ne, e, r0, r0, p, false, p * Nh / P, (p + 1) * Nh / P, L.ST + 2 * r0,
-                             std::integral_constant<int, 2 * Nq>(), L, iface);
+        split(t, P, VB, p, e, b);
+        const int r0 = b * R;
+        row_sums<real, N, R>(d, ne, e, r0, r0, p, false, int(unsigned(p) * Nh / P), int(unsigned(p + 1) * Nh / P),
+                             L.ST + 2 * r0, std::integral_constant<int, 2 * Nq>(), L, iface);
       } else {
-        const int tf = t - nv, p = tf % P, rest = tf / P, e = rest / FB, r0 = (rest - e * FB) * R;
-        row_sums<real, N, R>(d, ne, e, r0, Nq + r0, p, true, p * Nq / P, (p + 1) * Nq / P, L.FT + 2 * r0,
-                             std::integral_constant<int, 2 * Nfq>(), L, iface);
+        split(t - nv, P, FB, p, e, b);
+        const int r0 = b * R;
+        row_sums<real, N, R>(d, ne, e, r0, Nq + r0, p, true, int(unsigned(p) * Nq / P), int(unsigned(p + 1) * Nq / P),
+                             L.FT + 2 * r0, std::integral_constant<int, 2 * Nfq>(), L, iface);
       }
     }
   }
@@ -691,7 +715,7 @@ template <typename real, int N, int P, class LT>
 __device__ __forceinline__ void sum_partials(int ne, LT &L) {
   constexpr int Nq = dim_Nq(N), Nh = dim_Nh(N), PF = face_chunks<N, P>();
   for (int i = phase_tid(); i < 3 * ne * Nh; i += blockDim.x) {
-    const int n = i % Nh;
+    const int n = int(unsigned(i) % unsigned(Nh));
     real r = L.R[i];
     if (n < Nq) {
 #pragma unroll
@@ -710,15 +734,16 @@ template <typename real, int N, int PS, class LT>
 __device__ __forceinline__ void lift_valu(int ne, LT &L) {
   constexpr int Np = dim_Np(N), Nh = dim_Nh(N);
   for (int i = phase_tid(); i < 3 * ne * Np; i += blockDim.x) {
-    const int c = (i >= ne * Np) + (i >= 2 * ne * Np), r = i - c * ne * Np, e = r / Np, j = r - e * Np;
-    const real *Rc = L.R + c * ne * Nh + e * Nh;
+    const FieldTask<Np> k(i, ne * Np);
+    const real *Rc = L.R + __umul24(unsigned(k.c), unsigned(ne * Nh)) + __umul24(unsigned(k.e), unsigned(Nh));
+    const real *Vj = L.Vh + k.j;
     real ya = 0, yb = 0;
 #pragma unroll 32
     for (int n = 0; n < Nh; ++n) {
       real rn = Rc[n];
 #pragma unroll
       for (int p = 1; p < PS; ++p) rn += Rc[p * 3 * ne * Nh + n];
-      if (n & 1) yb += L.Vh[n * Np + j] * rn; else ya += L.Vh[n * Np + j] * rn;
+      if (n & 1) yb += Vj[n * Np] * rn; else ya += Vj[n * Np] * rn;
     }
     L.T[i] = ya + yb;
   }
@@ -798,11 +823,12 @@ template <typename real, int N, class LT>
 __device__ __forceinline__ void interface_tile(const InstDesc &d, int ne, LT &L) {
   constexpr int Nq = dim_Nq(N), Nfq = dim_Nfq(N), Nh = dim_Nh(N);
   for (int i = phase_tid(); i < ne * Nfq; i += blockDim.x) {
-    const int e = i / Nfq, f = i - e * Nfq, m = Nq + f;
+    const int e = int(unsigned(i) / unsigned(Nfq)), f = i - __umul24(unsigned(e), unsigned(Nfq)), m = Nq + f;
+    const int em = __umul24(unsigned(e), unsigned(Nh)) + m;
     real t0, t1, t2;
-    interface_terms<real>(L.rec + (e * Nh + m) * kNodeRec, L.nb + (e * Nfq + f) * 4, L.wf[f], L.nr[f], L.ns[f],
-                          real(d.g), d.flux, t0, t1, t2);
-    real *R0 = L.R + e * Nh + m;          // column part 0 of the three fields
+    interface_terms<real>(L.rec + __umul24(unsigned(em), unsigned(kNodeRec)), L.nb + 4 * i, L.wf[f], L.nr[f],
+                          L.ns[f], real(d.g), d.flux, t0, t1, t2);
+    real *R0 = L.R + em;                  // column part 0 of the three fields
     R0[0] = R0[0] + t0;
     R0[ne * Nh] = R0[ne * Nh] + t1;
     R0[2 * ne * Nh] = R0[2 * ne * Nh] + t2;
@@ -912,13 +938,14 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
   }
   // one task per (field, element, mode)
   for (int i = tid; i < 3 * ne * Np; i += nth) {
-    const int c = (i >= ne * Np) + (i >= 2 * ne * Np), j = i - c * ne * Np, e = j / Np, row = j - e * Np;
+    const FieldTask<Np> k(i, ne * Np);
     real rr;
     if constexpr (WADG) {
-      rr = -wadg_second<real, N>(L, L.R + c * ne * Nq + e * Nq, row);
+      rr = -wadg_second<real, N>(L, L.R + __umul24(unsigned(k.c), unsigned(ne * Nq)) +
+                                        __umul24(unsigned(k.e), unsigned(Nq)), k.j);
     } else {
-      const real *Mi = L.Minv + (e * Np + row) * Np;
-      const real *Tc = L.T + c * ne * Np + e * Np;
+      const real *Mi = L.Minv + __umul24(unsigned(k.r), unsigned(Np));   // row (e, j) of Minv_e
+      const real *Tc = L.T + (i - k.j);                                  // T[c][e][0..Np)
       real ra0 = 0, ra1 = 0;
 #pragma unroll 32
       for (int m = 0; m + 1 < Np; m += 2) {
@@ -928,7 +955,8 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
       if (Np & 1) ra0 -= Mi[Np - 1] * Tc[Np - 1];
       rr = ra0 + ra1;
     }
-    const size_t o = size_t(c) * splane + size_t(k0) * Np + j;
+    // global index: field c's plane, the tile's first element, then r (zero-extended)
+    const size_t o = size_t(unsigned(k.c)) * splane + size_t(k0) * Np + unsigned(k.r);
     if (a.mode == kRhs) {
       rhs_out[o] = rr;
     } else {
