@@ -57,7 +57,8 @@ def tile_words(N: int, E: int, P: int = 2) -> int:
     Np, Nq, Nfq = (N + 1) * (N + 2) // 2, (N + 1) ** 2, 3 * (N + 1)
     Nh = Nq + Nfq
     raw = max(8 * Nh, 3 * P * Nh + 3 * Np)
-    return E * (Nh * 12 + raw + 4 * Nfq + 6 * Np + Np * Np + 2 * Nq + Nh + Nfq)
+    rec = Nh * 12 + (4 if Nh % 2 == 0 else 0)      # node records, padded as the library pads them
+    return E * (rec + raw + 4 * Nfq + 6 * Np + Np * Np + 2 * Nq + Nh + Nfq)
 
 
 def shape_code(R: int, P: int) -> int:

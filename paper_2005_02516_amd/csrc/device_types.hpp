@@ -126,15 +126,24 @@ __host__ __device__ constexpr int raw_words(int D, int P) {
   return 8 * dim_Nh(D) > 3 * P * dim_Nh(D) + 3 * dim_Np(D) ? 8 * dim_Nh(D) : 3 * P * dim_Nh(D) + 3 * dim_Np(D);
 }
 
+// Reals of one element's node records in LDS: Nh records of kNodeRec, padded so that the
+// stride is an odd multiple of 4 words.  The residual's lanes read the records of up to
+// eight elements at one column at once; with such a stride their 16-byte reads fall on
+// eight different groups of four banks (an even multiple, e.g. 336 at N=3, puts elements
+// two apart on the same banks).
+__host__ __device__ constexpr int rec_stride(int D) {
+  return dim_Nh(D) * kNodeRec + (dim_Nh(D) % 2 == 0 ? 4 : 0);
+}
+
 // Words (of the bulk precision) of LDS one tile of E elements of kind D needs (the
 // reference block is held separately, once per workgroup).  Modal kinds: node records
-// [E][Nh][kNodeRec] | raw block [E][raw_words] | neighbour values [E][Nfq][4] | state, RK
+// [E][rec_stride] | raw block [E][raw_words] | neighbour values [E][Nfq][4] | state, RK
 // register [3][E][Np] each | static block [E][stat_words].  DG-SBP: node records | two
 // residual partials [2][3][E][Nh] | neighbour values | state, RK register [3][E][Nq] each |
 // static block.
 __host__ __device__ constexpr int tile_words(int D, int E, bool wadg = false, int P = 2) {
-  return key_sbp(D) ? E * (dim_Nh(D) * kNodeRec + 6 * dim_Nh(D) + 4 * dim_Nfq(D) + 6 * dim_Nq(D) + stat_words(D))
-                    : E * (dim_Nh(D) * kNodeRec + raw_words(D, P) + 4 * dim_Nfq(D) + 6 * dim_Np(D) +
+  return key_sbp(D) ? E * (rec_stride(D) + 6 * dim_Nh(D) + 4 * dim_Nfq(D) + 6 * dim_Nq(D) + stat_words(D))
+                    : E * (rec_stride(D) + raw_words(D, P) + 4 * dim_Nfq(D) + 6 * dim_Np(D) +
                            stat_words(D, wadg));
 }
 

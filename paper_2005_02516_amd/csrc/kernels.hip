@@ -180,7 +180,7 @@ struct Lds {
     nr = wf + Nfq;
     ns = nr + Nfq;
     rec = tile;
-    raw = rec + E * Nh * kNodeRec;
+    raw = rec + E * rec_stride(N);
     nb = raw + E * raw_words(N, P);
     U = nb + 4 * E * Nfq;
     DU = U + 3 * E * Np;
@@ -399,7 +399,7 @@ __device__ __forceinline__ void project_tile(const InstDesc &d, int k0, int ne, 
     if (to_records) {
       typedef real real4 __attribute__((ext_vector_type(4)));
       const real hr = real(h), ur = real(v2), vr = real(v3), gr = real(d.g);
-      real4 *rec = reinterpret_cast<real4 *>(L.rec + i * kNodeRec);
+      real4 *rec = reinterpret_cast<real4 *>(L.rec + __umul24(unsigned(e), unsigned(rec_stride(N))) + n * kNodeRec);
       rec[0] = real4{real(0.5) * hr * ur, real(0.5) * hr * vr, real(0.5) * ur, real(0.5) * vr};
       rec[2] = real4{real(0.5) * gr * hr, real(dH), hr, real(0)};
     } else {
@@ -576,7 +576,7 @@ __device__ __forceinline__ void row_sums(const InstDesc &d, int ne, int e, int r
                                          int n_lo, int n_hi, const real *Stab, LD ld2, LT &L, bool iface) {
   constexpr int Nfq = dim_Nfq(N), Nh = dim_Nh(N);
   typedef real real4 __attribute__((ext_vector_type(4)));
-  const real *rbase = L.rec + __umul24(unsigned(e), unsigned(Nh * kNodeRec));
+  const real *rbase = L.rec + __umul24(unsigned(e), unsigned(rec_stride(N)));
   real hu[R], hv[R], u[R], v[R], gh[R], rx[R], sx[R], ry[R], sy[R], a0[R], a1[R], a2[R];
   real b1[R], b2[R], q1[R], q2[R];
 #pragma unroll
@@ -657,6 +657,13 @@ __device__ __forceinline__ void residual_tile(const InstDesc &d, int ne, LT &L, 
     e = int(rest / rows);
     b = int(rest) - __umul24(unsigned(e), rows);
   };
+  // chunk slowest: task t = (p ne + e) rows + b with per = ne rows tasks per chunk, P <= 4
+  auto split_slow = [](int t, int per, unsigned rows, int &p, int &e, int &b) {
+    p = (t >= per) + (t >= 2 * per) + (t >= 3 * per);
+    const unsigned rest = unsigned(t - __umul24(unsigned(p), unsigned(per)));
+    e = int(rest / rows);
+    b = int(rest) - __umul24(unsigned(e), rows);
+  };
   for (int t = tid; t < ntask; t += nth) {
     if constexpr (wide_kind(N)) {
       constexpr int C = residual_chunk(N, P);
@@ -670,14 +677,17 @@ __device__ __forceinline__ void residual_tile(const InstDesc &d, int ne, LT &L, 
       row_sums<real, N, R>(d, ne, e, r0, face ? Nq + r0 : r0, p, face, n_lo, n_hi,
                            (face ? L.FT : L.ST) + 2 * r0, face ? 2 * Nfq : 2 * Nq, L, iface);
     } else {
+      // column chunk slowest: a wave's lanes then share one column range (the node records
+      // of its columns are read by several elements at once, the operator table's rows by
+      // consecutive row blocks), where chunk-fastest lanes read columns Nh / P apart
       int p, e, b;
       if (t < nv) {
-        split(t, P, VB, p, e, b);
+        split_slow(t, ne * VB, VB, p, e, b);
         const int r0 = b * R;
         row_sums<real, N, R>(d, ne, e, r0, r0, p, false, int(unsigned(p) * Nh / P), int(unsigned(p + 1) * Nh / P),
                              L.ST + 2 * r0, std::integral_constant<int, 2 * Nq>(), L, iface);
       } else {
-        split(t - nv, P, FB, p, e, b);
+        split_slow(t - nv, ne * FB, FB, p, e, b);
         const int r0 = b * R;
         row_sums<real, N, R>(d, ne, e, r0, Nq + r0, p, true, int(unsigned(p) * Nq / P), int(unsigned(p + 1) * Nq / P),
                              L.FT + 2 * r0, std::integral_constant<int, 2 * Nfq>(), L, iface);
@@ -826,7 +836,7 @@ __device__ __forceinline__ void interface_tile(const InstDesc &d, int ne, LT &L)
     const int e = int(unsigned(i) / unsigned(Nfq)), f = i - __umul24(unsigned(e), unsigned(Nfq)), m = Nq + f;
     const int em = __umul24(unsigned(e), unsigned(Nh)) + m;
     real t0, t1, t2;
-    interface_terms<real>(L.rec + __umul24(unsigned(em), unsigned(kNodeRec)), L.nb + 4 * i, L.wf[f], L.nr[f],
+    interface_terms<real>(L.rec + __umul24(unsigned(e), unsigned(rec_stride(N))) + m * kNodeRec, L.nb + 4 * i, L.wf[f], L.nr[f],
                           L.ns[f], real(d.g), d.flux, t0, t1, t2);
     real *R0 = L.R + em;                  // column part 0 of the three fields
     R0[0] = R0[0] + t0;
@@ -882,7 +892,8 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
   for (int i = tid; i < ne * Nh && !mid; i += nth) {
     const real h = L.raw[i], u = L.raw[ne * Nh + i], v = L.raw[2 * ne * Nh + i], dH = L.raw[3 * ne * Nh + i];
     typedef real real4 __attribute__((ext_vector_type(4)));
-    real4 *rec = reinterpret_cast<real4 *>(L.rec + i * kNodeRec);
+    const int e = int(unsigned(i) / unsigned(Nh)), n = i - __umul24(unsigned(e), unsigned(Nh));
+    real4 *rec = reinterpret_cast<real4 *>(L.rec + __umul24(unsigned(e), unsigned(rec_stride(N))) + n * kNodeRec);
     rec[0] = real4{real(0.5) * h * u, real(0.5) * h * v, real(0.5) * u, real(0.5) * v};
     rec[1] = real4{L.raw[4 * ne * Nh + i], L.raw[5 * ne * Nh + i], L.raw[6 * ne * Nh + i], L.raw[7 * ne * Nh + i]};
     rec[2] = real4{real(0.5) * g * h, dH, h, real(0)};
@@ -1220,7 +1231,7 @@ struct LdsSbp {
     fvol = ns + Nfq;              // volume node of face node f (integer-valued reals)
     vface = fvol + Nfq;           // face node of volume node n, or -1
     rec = tile;
-    R = rec + E * Nh * kNodeRec;  // two column-part partials [2][3][E][Nh]
+    R = rec + E * rec_stride(D);  // two column-part partials [2][3][E][Nh]
     nb = R + 6 * E * Nh;
     U = nb + 4 * E * Nfq;
     DU = U + 3 * E * Nq;
@@ -1300,7 +1311,7 @@ __device__ __forceinline__ void sbp_tile(const StageArgs &a, const InstDesc &d, 
     const double u = hu / h, v = hv / h;
     const int e = i / Nq, q = i - e * Nq;
     typedef real real4 __attribute__((ext_vector_type(4)));
-    real4 *rec = reinterpret_cast<real4 *>(L.rec + (e * Nh + q) * kNodeRec);
+    real4 *rec = reinterpret_cast<real4 *>(L.rec + e * rec_stride(D) + q * kNodeRec);
     rec[0] = real4{real(0.5 * hu), real(0.5 * hv), real(0.5 * u), real(0.5 * v)};
     rec[1] = real4{L.geo[i], L.geo[ne * Nq + i], L.geo[2 * ne * Nq + i], L.geo[3 * ne * Nq + i]};
     rec[2] = real4{real(0.5) * g * real(h), real(eta), real(h), real(0)};
@@ -1312,8 +1323,8 @@ __device__ __forceinline__ void sbp_tile(const StageArgs &a, const InstDesc &d, 
   for (int i = tid; i < ne * Nfq * 3; i += nth) {
     const int quad = i % 3, ef = i / 3, e = ef / Nfq, f = ef - e * Nfq;
     typedef real real4 __attribute__((ext_vector_type(4)));
-    const real4 *srcr = reinterpret_cast<const real4 *>(L.rec + (e * Nh + int(L.fvol[f])) * kNodeRec);
-    reinterpret_cast<real4 *>(L.rec + (e * Nh + Nq + f) * kNodeRec)[quad] = srcr[quad];
+    const real4 *srcr = reinterpret_cast<const real4 *>(L.rec + e * rec_stride(D) + int(L.fvol[f]) * kNodeRec);
+    reinterpret_cast<real4 *>(L.rec + e * rec_stride(D) + (Nq + f) * kNodeRec)[quad] = srcr[quad];
   }
   __syncthreads();
   residual_tile<real, D, 1, 2>(d, ne, L, true);
