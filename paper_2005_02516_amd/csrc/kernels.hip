@@ -1447,11 +1447,7 @@ const void *ESDG_UNIT_FN(ESDG_UNIT_REAL, ESDG_UNIT_WADG)(int cm, bool multi, boo
   using real = ESDG_UNIT_REAL;
   constexpr bool W = ESDG_UNIT_WADG != 0;
   // one variant-0 kind, vector-ALU contractions and its default shape: that kind's own build
-  // (float launches of one stage run the multi-stage build, so float has no per-stage one)
-  if (kind >= 1 && kind <= 5 && cm == kValu && !v1 && !shapes) {
-    if (multi) return kind_fn<true>(kind);
-    if constexpr (std::is_same<real, double>::value) return kind_fn<false>(kind);
-  }
+  if (kind >= 1 && kind <= 5 && cm == kValu && !v1 && !shapes) return multi ? kind_fn<true>(kind) : kind_fn<false>(kind);
   if (shapes)                      // vector-ALU contractions, variant-0 kinds
     return multi ? reinterpret_cast<const void *>(&stage_kernel<real, kValu, W, true, false, true>)
                  : reinterpret_cast<const void *>(&stage_kernel<real, kValu, W, false, false, true>);
@@ -1463,14 +1459,17 @@ const void *ESDG_UNIT_FN(ESDG_UNIT_REAL, ESDG_UNIT_WADG)(int cm, bool multi, boo
 // ---------------------------------------------------------------- host launchers
 
 // The stage kernel for a precision, contraction mode, mass inverse and launch kind (one
-// launch per stage, or all stages of a step call in one cooperative launch).  One launch
-// per stage uses the leaner per-stage instantiation, except for the FP32 vector-ALU kernel:
-// there the multi-stage instantiation (which runs as a per-stage kernel when given no
-// progress counts) was measured faster on balance (same box: N=4 1.4 %, N=5 5 %, the
-// mixed-degree ensemble 11 %; the per-stage build is faster only at N=3, by 8 %), while
-// the per-stage build is 7-11 % faster in FP64 and 6 % with split-bf16 contractions.
+// launch per stage, or all stages of a step call in one multi-stage launch).  One launch
+// per stage uses the leaner per-stage instantiation, except for the FP32 vector-ALU kernel
+// of several kinds or tile shapes: there the multi-stage instantiation (which runs as a
+// per-stage kernel when given no progress counts) was measured faster on balance (same
+// box: N=4 1.4 %, N=5 5 %, the mixed-degree ensemble 11 %), while the per-stage build is
+// 7-11 % faster in FP64 and 6 % with split-bf16 contractions.  The single-kind builds
+// take their per-stage instantiation in both precisions (FP32 on one box: N=2 -7.5 %, N=3
+// -6.5 %, N=4 -2 %, N=5 -2.3 % against their multi-stage build, whose scalar registers
+// spill four to ten times as much).
 static const void *stage_fn(bool fp64, int cm, bool wadg, bool multi, bool v1, bool shapes, int kind) {
-  if (!fp64 && cm == kValu) multi = true;
+  if (!fp64 && cm == kValu && !(kind >= 1 && kind <= 5 && !v1 && !shapes)) multi = true;
   if (fp64)
     return wadg ? stage_fn_unit_double_1(cm, multi, v1, shapes, kind) : stage_fn_unit_double_0(cm, multi, v1, shapes, kind);
   return wadg ? stage_fn_unit_float_1(cm, multi, v1, shapes, kind) : stage_fn_unit_float_0(cm, multi, v1, shapes, kind);
