@@ -1460,16 +1460,13 @@ const void *ESDG_UNIT_FN(ESDG_UNIT_REAL, ESDG_UNIT_WADG)(int cm, bool multi, boo
 
 // The stage kernel for a precision, contraction mode, mass inverse and launch kind (one
 // launch per stage, or all stages of a step call in one multi-stage launch).  One launch
-// per stage uses the leaner per-stage instantiation, except for the FP32 vector-ALU kernel
-// of several kinds or tile shapes: there the multi-stage instantiation (which runs as a
-// per-stage kernel when given no progress counts) was measured faster on balance (same
-// box: N=4 1.4 %, N=5 5 %, the mixed-degree ensemble 11 %), while the per-stage build is
-// 7-11 % faster in FP64 and 6 % with split-bf16 contractions.  The single-kind builds
-// take their per-stage instantiation in both precisions (FP32 on one box: N=2 -7.5 %, N=3
-// -6.5 %, N=4 -2 %, N=5 -2.3 % against their multi-stage build, whose scalar registers
-// spill four to ten times as much).
+// per stage runs the per-stage instantiation, built without the waits, resident tiles and
+// coherent pushes: its scalar registers spill far less (FP32 all kinds 36 against 102),
+// and each reload of a spilled one is a vector instruction.  (FP32 once ran its
+// multi-stage instantiation for single stages as well, measured faster then; with the
+// single-kind builds and the current task layout the per-stage one is faster on one box:
+// N=1..5 by 11, 7.5, 6.5, 2 and 2.3 %, the mixed-degree ensemble by 5 %.)
 static const void *stage_fn(bool fp64, int cm, bool wadg, bool multi, bool v1, bool shapes, int kind) {
-  if (!fp64 && cm == kValu && !(kind >= 1 && kind <= 5 && !v1 && !shapes)) multi = true;
   if (fp64)
     return wadg ? stage_fn_unit_double_1(cm, multi, v1, shapes, kind) : stage_fn_unit_double_0(cm, multi, v1, shapes, kind);
   return wadg ? stage_fn_unit_float_1(cm, multi, v1, shapes, kind) : stage_fn_unit_float_0(cm, multi, v1, shapes, kind);
