@@ -27,6 +27,9 @@ HIPFLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # packed FP32 instructions are kept out of every code object
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiplies and adds fuse into FMAs within one expression only, so that every build of
+    # a kernel (per-stage, multi-stage, single-kind) rounds the same source the same way
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-result",
 ]
 

@@ -489,22 +489,26 @@ __device__ __forceinline__ void fetch_tile(const StageArgs &a, const InstDesc &d
   const size_t splane = size_t(d.K) * Np;
   auto words = [](const void *p) { return static_cast<const uint32_t *>(p); };
   auto lwords = [](real *p) { return reinterpret_cast<uint32_t *>(p); };
-  if (a.mode != kProject) {
+  // the multi-stage build runs RK stages only, on the instance buffers (see stage_tile)
+  const int mode = MULTI ? int(kStage) : a.mode;
+  const void *ext_ut = MULTI ? nullptr : a.ext_ut, *ext_state = MULTI ? nullptr : a.ext_state;
+  const void *ext_nbx = MULTI ? nullptr : a.ext_nbx;
+  if (mode != kProject) {
     // u~ and the metric factors are stored tile-blocked ([4][ne][Nh] per tile), one copy each
     const size_t base = size_t(k0) * 4 * Nh;
-    const void *ut = a.ext_ut ? a.ext_ut : d.ut[a.in_buf];
+    const void *ut = ext_ut ? ext_ut : d.ut[a.in_buf];
     async_copy_words(lwords(L.raw), words(static_cast<const real *>(ut) + base), 4 * ne * Nh * W);
     async_copy_words(lwords(L.raw + 4 * ne * Nh), words(static_cast<const real *>(d.geo) + base), 4 * ne * Nh * W);
   }
-  if (a.mode == kStage) {
+  if (mode == kStage) {
     const real *uh = static_cast<const real *>(d.uh);
     const real *du = static_cast<const real *>(d.du);
     for (int c = 0; c < 3; ++c) {
       async_copy_words(lwords(L.U + c * ne * Np), words(uh + c * splane + size_t(k0) * Np), ne * Np * W);
       async_copy_words(lwords(L.DU + c * ne * Np), words(du + c * splane + size_t(k0) * Np), ne * Np * W);
     }
-  } else if (a.mode == kProject) {
-    const real *src = static_cast<const real *>(a.ext_state ? a.ext_state : d.uh);
+  } else if (mode == kProject) {
+    const real *src = static_cast<const real *>(ext_state ? ext_state : d.uh);
     for (int c = 0; c < 3; ++c)
       async_copy_words(lwords(L.U + c * ne * Np), words(src + c * splane + size_t(k0) * Np), ne * Np * W);
   }
@@ -513,12 +517,12 @@ __device__ __forceinline__ void fetch_tile(const StageArgs &a, const InstDesc &d
     // stage copies only the part beyond the first kStatRegs words per thread here; that head
     // goes through registers and lands in LDS after the residual (stage_tile).
     constexpr int SW = stat_words(N, WADG);
-    const int nstat = ne * SW * W, head = a.mode == kProject ? 0 : stat_head<real>(nstat);
+    const int nstat = ne * SW * W, head = mode == kProject ? 0 : stat_head<real>(nstat);
     async_copy_words(lwords(L.Minv) + head, words(static_cast<const real *>(d.stat) + size_t(k0) * SW) + head,
                      nstat - head);
   }
-  if (a.mode != kProject) {        // neighbour values, pushed here by the neighbours' projections
-    const void *nbx = a.ext_nbx ? a.ext_nbx : d.nbx[a.in_buf];
+  if (mode != kProject) {          // neighbour values, pushed here by the neighbours' projections
+    const void *nbx = ext_nbx ? ext_nbx : d.nbx[a.in_buf];
     const uint32_t *src = words(static_cast<const real *>(nbx) + size_t(k0) * Nfq * 4);
     if (MULTI && a.progress)       // multi-stage launch: written during this kernel, maybe on another XCD
       async_copy_words<kCpolAgent>(lwords(L.nb), src, ne * Nfq * 4 * W);
@@ -860,6 +864,11 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
   const real g = real(d.g);
   const bool mid = res & kResMid;                // resident tile after its first stage
   const bool keep = (res & kResident) && !(res & kResLast);   // state stays in LDS only
+  // The multi-stage build runs only multi-stage launches (and their residency probe, which
+  // returns before any tile): RK stages on the instance buffers.  Taking that as given here
+  // compiles the projection-only and RHS paths and the external buffers out of it, whose
+  // addresses would otherwise stay live in scalar registers (and spill) across the stage.
+  const int mode = MULTI ? int(kStage) : a.mode;
   // a resident tile after its first stage has everything but the neighbour values in LDS;
   // it fetches those after the pair loop, once its neighbours have pushed them
   if (!mid) fetch_tile<real, N, WADG, MULTI>(a, d, k0, ne, L);
@@ -870,14 +879,14 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
   constexpr int SR = StatRegs<real>::value;
   const uint32_t *sg = static_cast<const uint32_t *>(d.stat) + size_t(k0) * stat_words(N, WADG) * W;
   uint32_t sreg[SR];
-  if (a.mode != kProject && !mid) {
+  if (mode != kProject && !mid) {
 #pragma unroll
     for (int j = 0; j < SR; ++j) {
       const int v = tid + j * nth;
       sreg[j] = v < head ? sg[v] : 0u;
     }
   }
-  if (a.mode == kProject) {
+  if (!MULTI && mode == kProject) {
     __syncthreads();
     project_tile<real, N, CM, WADG>(d, k0, ne, L, static_cast<real *>(a.ext_ut ? a.ext_ut : d.ut[a.out_buf]),
                               static_cast<real *>(a.ext_nbx ? a.ext_nbx : d.nbx[a.out_buf]), a.flag,
@@ -941,7 +950,7 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
   const size_t splane = size_t(d.K) * Np;
   real *uh = static_cast<real *>(d.uh);
   real *du = static_cast<real *>(d.du);
-  real *rhs_out = static_cast<real *>(a.ext_rhs);
+  real *rhs_out = static_cast<real *>(MULTI ? nullptr : a.ext_rhs);
   const real ra = real(a.rk_a), rdt = real(d.dt), rb = real(a.rk_b);
   if constexpr (WADG) {            // first factor into the residual block (dead after the lift)
     wadg_first<real, N>(ne, L, L.T, L.R);
@@ -968,7 +977,7 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
     }
     // global index: field c's plane, the tile's first element, then r (zero-extended)
     const size_t o = size_t(unsigned(k.c)) * splane + size_t(k0) * Np + unsigned(k.r);
-    if (a.mode == kRhs) {
+    if (mode == kRhs) {
       rhs_out[o] = rr;
     } else {
       const real dn = ra * L.DU[i] + rdt * rr;
@@ -981,7 +990,7 @@ __device__ __forceinline__ bool stage_tile(const StageArgs &a, const InstDesc &d
       L.U[i] = un;
     }
   }
-  if (a.mode == kStage) {
+  if (mode == kStage) {
     __syncthreads();
     project_tile<real, N, CM, WADG>(d, k0, ne, L, static_cast<real *>(d.ut[a.out_buf]),
                               static_cast<real *>(d.nbx[a.out_buf]), a.flag, MULTI && a.progress != nullptr, res);
